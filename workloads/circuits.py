@@ -1,0 +1,251 @@
+"""Gate lists for the UCCSD and hardware-efficient ansatze.
+
+A gate list is the contract shared by the oracle and the HIP library: both
+apply exactly the same sequence of one-qubit gates (2x2) and nearest-neighbour
+two-qubit gates (4x4, row index 2*i_q0 + i_q1 with q1 = q0 + 1).
+
+UCCSD (Methods, "Unitary coupled cluster" and "The implementation of UCCSD
+with matrix product states"): each excitation generator theta (tau - tau^+) is
+Jordan-Wigner mapped to i * sum_k c_k P_k with mutually commuting strings, and
+first-order Trotterisation turns the ansatz into a product of Pauli
+exponentials exp(i theta c_k P_k).  Each exponential is compiled to a basis
+change, a nearest-neighbour parity ladder, a Z rotation and the inverse
+ladder; identity qubits inside the support are crossed by SWAPs so that the
+parity skips them.
+
+Hardware-efficient ansatz (Results, "Peak performance"; Discussions): layers
+of Ry/Rz on every qubit followed by CNOTs on every neighbouring pair
+(brickwork: even pairs, then odd pairs).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .hamiltonian import (
+    CODE_I, CODE_X, CODE_Y, CODE_Z, _expand_monomials, _masks_to_codes,
+    _n_words, _reduce,
+)
+
+
+@dataclass
+class Gate:
+    q0: int
+    q1: int  # -1 for a one-qubit gate, else q0 + 1
+    u: np.ndarray  # (2,2) or (4,4) complex
+
+
+_SQ2 = 1.0 / np.sqrt(2.0)
+
+
+def gate_h():
+    return np.array([[_SQ2, _SQ2], [_SQ2, -_SQ2]], dtype=complex)
+
+
+def gate_sdg():
+    return np.array([[1, 0], [0, -1j]], dtype=complex)
+
+
+def gate_rx(t):
+    c, s = np.cos(t / 2), np.sin(t / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=complex)
+
+
+def gate_ry(t):
+    c, s = np.cos(t / 2), np.sin(t / 2)
+    return np.array([[c, -s], [s, c]], dtype=complex)
+
+
+def gate_rz(t):
+    return np.array([[np.exp(-0.5j * t), 0], [0, np.exp(0.5j * t)]], dtype=complex)
+
+
+def gate_cnot():
+    """Control q0, target q1 (row index 2*i_q0 + i_q1)."""
+    m = np.eye(4, dtype=complex)
+    m[2:, 2:] = [[0, 1], [1, 0]]
+    return m
+
+
+def gate_swap():
+    m = np.zeros((4, 4), dtype=complex)
+    m[0, 0] = m[3, 3] = 1
+    m[1, 2] = m[2, 1] = 1
+    return m
+
+
+# --------------------------------------------------------------------------
+# Pauli exponentials
+# --------------------------------------------------------------------------
+
+def pauli_exponential_gates(code: np.ndarray, phi: float) -> list[Gate]:
+    """Nearest-neighbour gates for exp(i phi P), P given by per-qubit codes."""
+    code = np.asarray(code)
+    sup = np.nonzero(code)[0]
+    if sup.size == 0:
+        return []  # global phase only
+    m, n = int(sup[0]), int(sup[-1])
+    pre, post = [], []
+    for q in sup:
+        c = int(code[q])
+        if c == CODE_X:
+            pre.append(Gate(int(q), -1, gate_h()))
+            post.append(Gate(int(q), -1, gate_h()))
+        elif c == CODE_Y:
+            b = gate_h() @ gate_sdg()  # maps Y to Z: b Y b^+ = Z
+            pre.append(Gate(int(q), -1, b))
+            post.append(Gate(int(q), -1, b.conj().T))
+    ladder = []
+    for q in range(m, n):
+        if code[q + 1] != CODE_I:
+            ladder.append(Gate(q, q + 1, gate_cnot()))
+        else:
+            ladder.append(Gate(q, q + 1, gate_swap()))
+    rot = Gate(n, -1, np.diag([np.exp(1j * phi), np.exp(-1j * phi)]).astype(complex))
+    return pre + ladder + [rot] + ladder[::-1] + post
+
+
+# --------------------------------------------------------------------------
+# UCCSD
+# --------------------------------------------------------------------------
+
+def uccsd_excitations(n_qubits: int, n_electrons: int):
+    """Spin-conserving singles (i, a) then doubles (i, j, a, b), lexicographic.
+
+    Spin orbital j has spin j % 2; occupied = 0 .. n_electrons-1.
+    """
+    occ = range(n_electrons)
+    vir = range(n_electrons, n_qubits)
+    singles = [(i, a) for i in occ for a in vir if i % 2 == a % 2]
+    doubles = []
+    for i in occ:
+        for j in occ:
+            if j <= i:
+                continue
+            for a in vir:
+                for b in vir:
+                    if b <= a:
+                        continue
+                    if sorted((i % 2, j % 2)) == sorted((a % 2, b % 2)):
+                        doubles.append((i, j, a, b))
+    return singles, doubles
+
+
+def _generator_strings(n_qubits, orbs_left, orbs_right):
+    """JW strings of tau - tau^+ with tau = a+_{l0} [a+_{l1}] a_{r0} [a_{r1}].
+
+    Returns (codes, c) with tau - tau^+ = i * sum_k c_k P_k.
+    """
+    words = _n_words(n_qubits)
+    ops = list(orbs_left) + list(orbs_right)
+    dag = [True] * len(orbs_left) + [False] * len(orbs_right)
+    one = np.ones(1, dtype=complex)
+    k1, v1 = _expand_monomials([np.array([o]) for o in ops], dag, one, words)
+    # tau^+ = reversed product with daggers flipped
+    ops_h = ops[::-1]
+    dag_h = [not d for d in dag[::-1]]
+    k2, v2 = _expand_monomials([np.array([o]) for o in ops_h], dag_h, -one, words)
+    keys, vals = _reduce(np.concatenate([k1, k2]), np.concatenate([v1, v2]))
+    keep = np.abs(vals) > 1e-14
+    keys, vals = keys[keep], vals[keep]
+    assert np.max(np.abs(vals.real)) < 1e-14, "generator must be anti-Hermitian"
+    codes = _masks_to_codes(keys, n_qubits, words)
+    return codes, vals.imag.copy()
+
+
+def uccsd_gates(n_qubits: int, n_electrons: int, theta: np.ndarray) -> list[Gate]:
+    """First-order Trotterised UCCSD: prod_ex prod_k exp(i theta_ex c_k P_k)."""
+    singles, doubles = uccsd_excitations(n_qubits, n_electrons)
+    exc = [((a,), (i,)) for (i, a) in singles] + [((a, b), (i, j)) for (i, j, a, b) in doubles]
+    theta = np.asarray(theta, dtype=float)
+    assert theta.size == len(exc), (theta.size, len(exc))
+    gates: list[Gate] = []
+    for t, (left, right) in zip(theta, exc):
+        codes, c = _generator_strings(n_qubits, left, right)
+        for code, ck in zip(codes, c):
+            gates.extend(pauli_exponential_gates(code, float(t * ck)))
+    return gates
+
+
+def uccsd_n_params(n_qubits: int, n_electrons: int) -> int:
+    s, d = uccsd_excitations(n_qubits, n_electrons)
+    return len(s) + len(d)
+
+
+# --------------------------------------------------------------------------
+# hardware-efficient brickwork
+# --------------------------------------------------------------------------
+
+def brickwork_gates(n_qubits: int, angles: np.ndarray) -> list[Gate]:
+    """angles[l, q] = (ry, rz): per layer Ry then Rz on every qubit, then
+    CNOT(q, q+1) for even q, then for odd q (control = lower index)."""
+    gates: list[Gate] = []
+    for layer in angles:
+        for q in range(n_qubits):
+            gates.append(Gate(q, -1, gate_ry(layer[q, 0])))
+            gates.append(Gate(q, -1, gate_rz(layer[q, 1])))
+        for start in (0, 1):
+            for q in range(start, n_qubits - 1, 2):
+                gates.append(Gate(q, q + 1, gate_cnot()))
+    return gates
+
+
+# --------------------------------------------------------------------------
+# gate-list simplification (exact: products of the given matrices)
+# --------------------------------------------------------------------------
+
+def fuse_gates(gates: list[Gate], n_qubits: int) -> list[Gate]:
+    """Merge consecutive 1q gates, fold them into the next 2q gate on that
+    qubit, merge consecutive 2q gates on the same pair and drop identities.
+    The product of the returned list equals the product of the input."""
+    pending: list[np.ndarray | None] = [None] * n_qubits
+    out: list[Gate] = []
+    last2: list[int] = [-1] * n_qubits  # index in out of last 2q gate touching q
+
+    def flush(q):
+        if pending[q] is not None:
+            if not np.allclose(pending[q], np.eye(2), atol=1e-15):
+                out.append(Gate(q, -1, pending[q]))
+                last2[q] = -1
+            pending[q] = None
+
+    for g in gates:
+        if g.q1 < 0:
+            pending[g.q0] = g.u if pending[g.q0] is None else g.u @ pending[g.q0]
+            continue
+        a, b = g.q0, g.q1
+        u = g.u
+        ua = pending[a] if pending[a] is not None else np.eye(2)
+        ub = pending[b] if pending[b] is not None else np.eye(2)
+        if pending[a] is not None or pending[b] is not None:
+            u = u @ np.kron(ua, ub)
+        pending[a] = pending[b] = None
+        j = last2[a]
+        if j >= 0 and j == last2[b] and out[j].q0 == a and out[j].q1 == b:
+            m = u @ out[j].u
+            out[j] = Gate(a, b, m)
+            if np.allclose(m, np.eye(4), atol=1e-14):
+                out[j] = None  # type: ignore[assignment]
+                last2[a] = last2[b] = -1
+            continue
+        out.append(Gate(a, b, u))
+        last2[a] = last2[b] = len(out) - 1
+    for q in range(n_qubits):
+        flush(q)
+    return [g for g in out if g is not None]
+
+
+def pack_gates(gates: list[Gate]):
+    """Flat arrays for the C ABI: q0[int32], q1[int32], u (G, 16, 2) float64
+    (2x2 gates occupy the first 4 entries)."""
+    G = len(gates)
+    q0 = np.array([g.q0 for g in gates], dtype=np.int32)
+    q1 = np.array([g.q1 for g in gates], dtype=np.int32)
+    u = np.zeros((G, 16, 2), dtype=np.float64)
+    for i, g in enumerate(gates):
+        flat = np.asarray(g.u, dtype=complex).ravel()
+        u[i, :flat.size, 0] = flat.real
+        u[i, :flat.size, 1] = flat.imag
+    return q0, q1, u
