@@ -1,0 +1,224 @@
+/*
+ * mps.h -- C ABI of the MI355X matrix-product-state energy evaluator.
+ *
+ * The library evaluates E(theta) = sum_k c_k <psi(theta)|P_k|psi(theta)> for a
+ * state held as a right-canonical matrix product state (MPS) of bond
+ * dimension D, following the paper's Methods:
+ *   - "MPS algorithm for quantum circuit simulation": right-canonical gauge
+ *     (Eq. rc), one-qubit gates (Eq. 1q), two-qubit gates by the Hastings
+ *     scheme: two-site contraction (Eq. C), lambda scaling (Eq. C~),
+ *     truncated SVD (Eq. svd) by the one-sided Jacobi method of Algorithm 1,
+ *     site update (Eq. Bl);
+ *   - "The implementation of UCCSD with matrix product states": Pauli-string
+ *     expectations from lambda^2 and transfer matrices (Eqs. expec1,
+ *     expec2), the energy as the coefficient-weighted sum of them.
+ *
+ * Conventions shared by every entry point
+ *   - Sites 0..N-1 are qubits 0..N-1; bond b sits left of site b; bond 0 and
+ *     bond N have dimension 1.  Site tensor B_q has shape (2, D_q, D_{q+1}),
+ *     row-major, complex numbers as (re, im) double pairs.
+ *   - Two-qubit gate matrices are 4x4 with row/column index 2*i_q0 + i_q1,
+ *     one-qubit gates 2x2; row-major (re, im) pairs.
+ *   - Pauli codes: 0 = I, 1 = X, 2 = Y, 3 = Z, one byte per qubit.
+ *   - Ownership: the caller owns every host array and may reuse it when the
+ *     call returns (the library copies).  The library owns all device memory
+ *     it allocates until the matching *_destroy.
+ *   - Streams: work is enqueued on the handle's stream (mps_config.stream, a
+ *     hipStream_t, or a stream the library creates when NULL).  Calls that
+ *     return host values synchronise that stream.
+ *   - Errors: every call returns an mps_status; on failure, output arguments
+ *     are left untouched and mps_last_error() (thread-local) describes the
+ *     failure.  MPS_ERR_ARG, MPS_ERR_BUDGET, MPS_ERR_NOCONV and
+ *     MPS_ERR_NONFINITE leave the MPS as it was before the call.
+ *     MPS_ERR_DEVICE poisons the handle: later calls on it return
+ *     MPS_ERR_DEVICE until mps_destroy.
+ *   - Threading: one handle is used by one thread at a time.
+ */
+#ifndef MPS_H_
+#define MPS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mps_state* mps_handle;
+typedef struct mps_psum* mps_pauli_sum;
+
+typedef enum {
+  MPS_OK = 0,
+  MPS_ERR_ARG = -1,       /* invalid argument or shape                          */
+  MPS_ERR_OOM = -2,       /* device allocation failed                           */
+  MPS_ERR_BUDGET = -3,    /* the handle's HBM budget would be exceeded          */
+  MPS_ERR_NOCONV = -4,    /* Jacobi SVD did not converge within the sweep limit */
+  MPS_ERR_NONFINITE = -5, /* NaN/Inf in an input or an SVD                      */
+  MPS_ERR_DEVICE = -6,    /* HIP runtime error (handle poisoned)                */
+  MPS_ERR_STATE = -7      /* call not valid in the current state                */
+} mps_status;
+
+/* Arithmetic of the environment (transfer-matrix) products.  Gates, SVDs,
+ * canonicalisation and the final energy sum are always FP64. */
+typedef enum {
+  MPS_PREC_C128 = 0,       /* complex128 on FP64 MFMA                              */
+  MPS_PREC_C64 = 1,        /* complex64 on FP32 MFMA                               */
+  MPS_PREC_SPLIT_BF16 = 2, /* FP32 values split into bf16 hi+lo, FP32 accumulate   */
+  MPS_PREC_SPLIT_F16 = 3   /* FP32 values split into scaled f16 hi+lo, FP32 accum. */
+} mps_precision;
+
+typedef struct {
+  int32_t n_qubits;          /* N >= 1                                             */
+  int32_t max_bond;          /* D >= 1: bond dimensions are capped at D            */
+  double svd_cutoff;         /* keep sigma_j > svd_cutoff * ||sigma||_2 (Methods,
+                                two-qubit gate: "truncate the small singular
+                                values below a certain threshold or simply
+                                reserve the largest few"); >= 0                   */
+  int32_t max_jacobi_sweeps; /* 0 = default (30)                                   */
+  const uint8_t* init_bits;  /* N bytes in {0,1}: initial product state; NULL = 0s */
+  void* stream;              /* hipStream_t to enqueue on; NULL = library-owned    */
+  size_t hbm_budget_bytes;   /* 0 = unlimited; otherwise device bytes the handle
+                                may hold (MPS, workspaces, environments)           */
+} mps_config;
+
+/* Create an MPS holding the product state |init_bits> (Methods, Hartree-Fock
+ * reference of the UCC ansatz: B^s = delta_{s,b}, all bonds of dimension 1,
+ * lambda = 1).  Allocates the site tensors at their maximal size
+ * min(D, 2^min(b, N-b)) per bond.  *out receives the handle. */
+mps_status mps_create(const mps_config* cfg, mps_handle* out);
+
+/* Release all device memory of the handle.  NULL is a no-op. */
+mps_status mps_destroy(mps_handle h);
+
+/* Return to the product state |bits> (NULL = |0..0>) keeping allocations. */
+mps_status mps_reset(mps_handle h, const uint8_t* bits);
+
+/* Apply one gate.  q1 < 0: one-qubit gate on q0 (Eq. 1q), u = 2x2.
+ * q1 = q0 + 1: two-qubit gate (Eqs. C, C~, svd, Bl) with truncation to
+ * min(D, #{sigma_j > cutoff ||sigma||}) singular values and renormalisation
+ * to unit norm, u = 4x4.  Any other q1 is MPS_ERR_ARG. */
+mps_status mps_apply_gate(mps_handle h, int32_t q0, int32_t q1, const double* u);
+
+/* Apply n gates in order.  u_packed holds 32 doubles per gate (a 4x4 complex
+ * matrix; a 2x2 gate uses the first 8).  Consecutive two-qubit gates on
+ * disjoint bonds are processed as one batch (one batched SVD).  On error the
+ * gates before the failing batch stay applied; *n_done (may be NULL)
+ * receives the number of gates applied. */
+mps_status mps_apply_gates(mps_handle h, int64_t n, const int32_t* q0, const int32_t* q1,
+                           const double* u_packed, int64_t* n_done);
+
+/* Restore the exact right-canonical gauge (Eq. rc), exact Schmidt values on
+ * every bond and unit norm: a left-to-right orthonormalisation sweep followed
+ * by a right-to-left SVD sweep, both by one-sided Jacobi.  Only round-off
+ * singular values (<= 1e-14 ||sigma||) are dropped. */
+mps_status mps_canonicalize(mps_handle h);
+
+/* Norm ||psi|| found by the last mps_canonicalize (1 for a normalised
+ * state). */
+mps_status mps_norm(mps_handle h, double* norm);
+
+/* Sum of the relative discarded weights sum_{j>k} sigma_j^2 / sum sigma_j^2
+ * of every truncating two-qubit gate since create/reset. */
+mps_status mps_discarded_weight(mps_handle h, double* weight);
+
+/* Current bond dimensions D_0 .. D_N (N+1 values). */
+mps_status mps_bond_dims(mps_handle h, int32_t* dims);
+
+/* Compile a Pauli sum sum_k coeffs[k] P_k on n_qubits qubits into a plan
+ * (Eq. expec2 generalised to every string: prefix and suffix transfer-matrix
+ * tries that share common sub-strings, meeting at one bond per string).
+ * codes is n_terms x n_qubits bytes.  The plan is independent of any handle
+ * with the same n_qubits. */
+mps_status mps_pauli_sum_create(int32_t n_qubits, int64_t n_terms, const uint8_t* codes,
+                                const double* coeffs, mps_pauli_sum* out);
+
+/* Release a plan.  NULL is a no-op. */
+mps_status mps_pauli_sum_destroy(mps_pauli_sum p);
+
+/* Planner statistics: numbers of left and right transfer-matrix updates and
+ * of distinct closing pairs per evaluation, and the meeting bond. */
+mps_status mps_pauli_sum_stats(mps_pauli_sum p, int64_t* n_left_updates, int64_t* n_right_updates,
+                               int64_t* n_closes, int32_t* meet_bond);
+
+/* Copy the plan out for inspection: the left trie (parent reference, site,
+ * letter per node; a parent < 0 is the root -(b+1) at bond b, i.e.
+ * diag(lambda_b^2)), the right trie (same, roots are identities at bond b,
+ * nodes hold transposed right environments) and, per term, the bond and the
+ * two references whose closing trace Tr(L R) gives <P_k>.  Arrays are sized
+ * by mps_pauli_sum_stats (left, right) and n_terms; any may be NULL. */
+mps_status mps_pauli_sum_export(mps_pauli_sum p, int32_t* left_parent, int32_t* left_site,
+                                int32_t* left_letter, int32_t* right_parent, int32_t* right_site,
+                                int32_t* right_letter, int32_t* close_bond, int32_t* close_left,
+                                int32_t* close_right);
+
+/* E = sum_k c_k Re<P_k> (Methods, UCC: the energy from the expectation
+ * values of the qubit Hamiltonian; Eqs. expec1/expec2 for each <P_k>).
+ * Canonicalises first if a gate was applied since the last
+ * mps_canonicalize.  The transfer-matrix products run in `prec`; the
+ * per-string values are summed in FP64 with compensation in string order, so
+ * the result does not depend on how strings are batched.  per_term, if not
+ * NULL, receives Re<P_k> for every k (n_terms doubles). */
+mps_status mps_expect_pauli_sum(mps_handle h, mps_pauli_sum p, mps_precision prec, double* energy,
+                                double* per_term);
+
+/* Copy site q's tensor to the host: *dl, *dr receive D_q, D_{q+1}; b (may be
+ * NULL) receives 2*D_q*D_{q+1} complex values as (re, im) pairs in
+ * [s][alpha][beta] order; lambda_left (may be NULL) receives the D_q
+ * singular values of bond q. */
+mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
+                           double* lambda_left);
+
+/* Overwrite site q's tensor and the singular values of bond q.  dl must equal
+ * D_{q} of the left neighbour's right bond (or 1 at q = 0) once all sites are
+ * imported; the library checks shapes against its capacity only.  Importing
+ * marks the state canonical: the caller asserts the imported tensors are in
+ * right-canonical form with Schmidt values (use mps_canonicalize otherwise). */
+mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, const double* b,
+                           const double* lambda_left);
+
+/* Standalone one-sided Jacobi SVD (Algorithm 1) of the n_vec vectors of
+ * length vec_len given row-major in `vectors` (host): the vectors are
+ * rotated pairwise until mutually orthogonal.  sigma receives the n_vec
+ * norms sorted descending; out_vectors (n_vec x vec_len, may be NULL)
+ * receives the normalised vectors in the same order (zero where sigma = 0);
+ * *sweeps (may be NULL) the number of sweeps.  For a matrix A whose rows are
+ * the vectors, A = U diag(sigma) W with W = out_vectors. */
+mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors, double* sigma,
+                          double* out_vectors, int32_t* sweeps);
+
+/* Timing of the transfer-matrix (environment update) kernels, measured with
+ * HIP events around each launch while enabled. */
+typedef struct {
+  double env_ms;            /* summed duration of environment-update launches  */
+  int64_t env_launches;     /* number of such launches                         */
+  double env_flops;         /* algorithmic FLOPs of those launches (4M complex) */
+  int64_t env_updates;      /* transfer-matrix updates performed               */
+  double close_ms;          /* summed duration of closing (trace) launches     */
+  double close_flops;       /* algorithmic FLOPs of the closing products       */
+  double expect_ms;         /* wall time of mps_expect_pauli_sum calls         */
+  double gates_ms;          /* wall time of gate application                   */
+  double canon_ms;          /* wall time of canonicalisation                   */
+  int64_t jacobi_sweeps;    /* total Jacobi sweeps executed                    */
+} mps_timing;
+
+mps_status mps_set_timing(mps_handle h, int32_t enabled); /* also resets counters */
+mps_status mps_get_timing(mps_handle h, mps_timing* out);
+
+/* Device bytes currently held by the handle. */
+mps_status mps_device_bytes(mps_handle h, size_t* bytes);
+
+/* Layout self-check of the matrix-core instructions used by the dense
+ * products: runs one 16x16x4 product of known operands in FP64 and in FP32
+ * on the device and writes each 16x16 result, read back through the lane
+ * layout the kernels assume, to out (2 x 256 doubles, row-major: FP64 first,
+ * then FP32). */
+mps_status mps_selftest_mfma(double* out);
+
+/* Thread-local description of the last error on this thread. */
+const char* mps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_H_ */

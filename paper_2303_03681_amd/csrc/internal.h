@@ -1,0 +1,153 @@
+// Internal interface between the host orchestration (mps_api.cpp) and the
+// device kernels (kernels.hip).  Descriptors are plain structs copied to
+// device memory; every size in them has been checked on the host against
+// the capacity of the buffers the pointers refer to.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mps {
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<double> { using type = double2; };
+template <> struct cplx_of<float> { using type = float2; };
+
+// ---------------------------------------------------------------- gates
+struct ThetaItem {        // Eq. (C) product B_q (2Dl x Dm) * [B_{q+1}^0 | B_{q+1}^1] (Dm x 2Dr)
+  const double2* bl;      // site q, [s][l][m]
+  const double2* br;      // site q+1, [s][m][r]
+  double2* theta;         // out: (2Dl x 2Dr) row-major, rows (s1,l), cols (s2,r)
+  int dl, dm, dr;
+};
+
+struct MixItem {          // Q mixing (Eq. C) and lambda row scaling (Eq. C~)
+  double2* c;             // in: theta, out: C (in place), (2Dl x 2Dr)
+  double2* w;             // out: C~ = lambda_l C, the Jacobi work matrix
+  const double* lam;      // lambda of bond q (Dl values)
+  const double2* q;       // 4x4 gate, row-major
+  double* fro2;           // out: ||C~||_F^2
+  int dl, dr;
+};
+
+struct JacItem {          // one-sided Jacobi on the n row vectors (length m) of w
+  double2* w;
+  const double* fro2;     // ||w||_F^2 (invariant under the rotations)
+  int* rot;               // rotation count per sweep [max_sweeps]
+  int* sweeps_done;       // single-launch mode: sweeps executed (negative: no convergence)
+  int n, m, wblk, nb;     // vectors, length, vectors per block, number of blocks (even)
+};
+
+enum FinalizeMode { FIN_GATE = 0, FIN_LEFT = 1, FIN_RIGHT = 2 };
+
+struct FinItem {          // norms, stable descending sort, truncation, output tensors
+  const double2* w;       // converged vectors (n x m)
+  double2* vec_out;       // FIN_GATE/FIN_RIGHT: [s][a][r] (k x m split at m/2);
+                          // FIN_LEFT: [e][a] (m x k)
+  double* lam_out;        // FIN_GATE/FIN_RIGHT: normalised singular values (k)
+  int* k_out;             // number kept
+  double* scale_out;      // 1 / ||sigma_1..k||
+  double* disc_out;       // relative discarded weight
+  int* status_out;        // 0 ok, 1 non-finite or zero
+  int n, m, cap;          // vectors, length, maximum k
+  double cutoff;
+  int mode;
+};
+
+struct TruncItem {        // Eq. (Bl): out (2Dl x k) = C (2Dl x 2Dr) * conj(V)^T * scale
+  const double2* c;
+  const double2* v;       // [s][a][r], k rows per s
+  double2* out;
+  const double* scale;
+  int rows, dr, k;        // rows = 2Dl
+};
+
+// ---------------------------------------------------------------- canonical form
+struct CanonLeftItem {    // W[beta][(s,alpha)] = sum_g B[s][g][beta] T[alpha][g]
+  const double2* b;       // site [s][g][beta], (2, Dg, Db)
+  const double2* t;       // carry (r x Dg)
+  double2* w;             // out (Db x 2r), row-major
+  int r, dg, db, s;
+};
+struct CanonCarryLeftItem {  // T'[a][beta] = sum_e conj(A[e][a]) W0[beta][e]
+  const double2* a;       // left-canonical tensor as (m x k), m = 2r
+  const double2* w0;      // M^T (Db x m)
+  double2* t;             // out (k x Db)
+  int k, m, db;
+};
+struct CanonRightItem {   // W[alpha][(s,b')] = sum_beta A[s][alpha][beta] T[beta][b']
+  const double2* a;       // site (2, Dl, Dm)
+  const double2* t;       // carry (Dm x r)
+  double2* w;             // out (Dl x 2r)
+  int dl, dm, r, s;
+};
+
+// ---------------------------------------------------------------- environments
+template <typename C2>
+struct EnvParent {        // X = L [A^0 | A^1]
+  const C2* l;            // (Dl x Dl)
+  C2* x;                  // (Dl x 2Dr)
+};
+template <typename C2>
+struct EnvChild {         // L' = sum_s A^{s+} (ph_s X^{s xor flip})
+  const C2* x;
+  C2* out;                // (Dr x Dr)
+  int letter;             // 0 I, 1 X, 2 Y, 3 Z
+};
+
+struct GramItem {         // G[a][b] = Re sum_x L_a[x] R_b[x]  (closing traces)
+  const void* const* lptr;
+  const void* const* rptr;
+  double* g;              // (nl x nr)
+  int nl, nr, kdim;
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_init_product(double2* const* sites, double* const* lam0, const uint8_t* bits,
+                               int n, hipStream_t s);
+hipError_t launch_gate1q(double2* b, const double2* u, int count, hipStream_t s);
+hipError_t launch_theta(const ThetaItem* items_dev, int items, int max_rows, int max_cols,
+                        hipStream_t s);
+hipError_t launch_mix(const MixItem* items_dev, int items, int max_dldr, hipStream_t s);
+hipError_t configure_jacobi_lds(size_t bytes);
+hipError_t launch_jacobi_block(const JacItem* items_dev, int items, int max_pairs, int round,
+                               int sweep, double eps_scale, size_t lds_bytes, hipStream_t s);
+hipError_t launch_jacobi_single(const JacItem* items_dev, int items, int max_sweeps,
+                                double eps_scale, size_t lds_bytes, hipStream_t s);
+hipError_t launch_finalize(const FinItem* items_dev, int items, hipStream_t s);
+hipError_t launch_trunc(const TruncItem* items_dev, int items, int max_rows, int max_k,
+                        hipStream_t s);
+hipError_t launch_canon_left(const CanonLeftItem* items_dev, int items, int max_db, int max_r,
+                             hipStream_t s);
+hipError_t launch_canon_carry_left(const CanonCarryLeftItem* items_dev, int items, int max_k,
+                                   int max_db, hipStream_t s);
+hipError_t launch_canon_right(const CanonRightItem* items_dev, int items, int max_dl, int max_r,
+                              hipStream_t s);
+hipError_t launch_fro2(const double2* w, int count, double* out, hipStream_t s);
+hipError_t launch_copy(double2* dst, const double2* src, size_t count, hipStream_t s);
+hipError_t launch_fill_ident(double2* dst, int d, hipStream_t s);
+
+// environment products: c128 on FP64 MFMA, c64 on FP32 MFMA
+hipError_t launch_env_gemm1_c128(const EnvParent<double2>* items, int count, const double2* site,
+                                 int dl, int dr, hipStream_t s);
+hipError_t launch_env_gemm2_c128(const EnvChild<double2>* items, int count, const double2* site,
+                                 int dl, int dr, hipStream_t s);
+hipError_t launch_env_gemm1_c64(const EnvParent<float2>* items, int count, const float2* site,
+                                int dl, int dr, hipStream_t s);
+hipError_t launch_env_gemm2_c64(const EnvChild<float2>* items, int count, const float2* site,
+                                int dl, int dr, hipStream_t s);
+
+hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr, int dl, int dr,
+                               int elem_bytes, hipStream_t s);
+hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,
+                        hipStream_t s);
+hipError_t launch_gram(const GramItem* items_dev, int items, int max_nl, int max_nr, int elem_bytes,
+                       hipStream_t s);
+hipError_t launch_gather(const double* g, const int64_t* gidx, double* per_term, int64_t n,
+                         hipStream_t s);
+hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n, double* out,
+                         hipStream_t s);
+hipError_t launch_selftest_mfma(double* out, hipStream_t s);
+
+}  // namespace mps

@@ -1,0 +1,873 @@
+// Device kernels of the MPS energy evaluation (gfx950).
+//
+//   init_product     product state B^s = delta_{s,b} (Methods, UCC: HF reference)
+//   gate1q           Eq. (1q)
+//   theta + mix      Eq. (C) as one batched MFMA GEMM, then the 4x4 gate mix and
+//                    the lambda row scale of Eq. (C~)
+//   jacobi_*         Algorithm 1 (one-sided Jacobi), block-parallel round-robin
+//   finalize         sigma_i = ||a_i||, stable descending sort, truncation,
+//                    normalised vectors -> B~_{q+1} = V (Eq. Bl) or canonical tensors
+//   trunc            Eq. (Bl): B~_q = C V^+, an MFMA GEMM
+//   canon_*          the GEMMs of the two canonicalisation sweeps
+//   env_gemm1/2      Eq. (expec2) transfer update L' = sum sigma A^{s+} L A^{s'}
+//   gram             closing traces Tr(L R) for all (prefix, suffix) pairs at a bond
+//   energy           compensated FP64 sum_k c_k <P_k> in string order
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "gemm_core.h"
+#include "internal.h"
+
+namespace mps {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+// =================================================================== state
+
+__global__ void init_product_kernel(double2* const* sites, double* const* lam, const uint8_t* bits,
+                                    int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) {
+    const int b = bits[q] ? 1 : 0;
+    sites[q][0] = make_double2(b == 0 ? 1.0 : 0.0, 0.0);
+    sites[q][1] = make_double2(b == 1 ? 1.0 : 0.0, 0.0);
+  }
+  if (q <= n) lam[q][0] = 1.0;
+}
+
+hipError_t launch_init_product(double2* const* sites, double* const* lam0, const uint8_t* bits,
+                               int n, hipStream_t s) {
+  hipLaunchKernelGGL(init_product_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, sites, lam0,
+                     bits, n);
+  return hipGetLastError();
+}
+
+// Eq. (1q): B^s <- sum_s' Q_{ss'} B^{s'}; count = Dl * Dr elements per physical index.
+__global__ void gate1q_kernel(double2* b, const double2* u, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double2 x0 = b[i], x1 = b[count + i];
+  const double2 u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+  const double2 a = cmul(u00, x0), bb = cmul(u01, x1), c = cmul(u10, x0), d = cmul(u11, x1);
+  b[i] = make_double2(a.x + bb.x, a.y + bb.y);
+  b[count + i] = make_double2(c.x + d.x, c.y + d.y);
+}
+
+hipError_t launch_gate1q(double2* b, const double2* u, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gate1q_kernel, dim3(cdiv(count, 256)), dim3(256), 0, s, b, u, count);
+  return hipGetLastError();
+}
+
+// =================================================================== Eq. (C)
+
+struct ThetaP {
+  using T = double;
+  using Ctx = ThetaItem;
+  static constexpr bool A_CONTIG_K = true, B_CONTIG_N = true, REAL_ONLY = false;
+  const ThetaItem* items;
+  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = 2 * c.dl;
+    N = 2 * c.dr;
+    K = c.dm;
+  }
+  __device__ static double2 loadA(const Ctx& c, int i, int k) { return c.bl[(size_t)i * c.dm + k]; }
+  __device__ static double2 loadB(const Ctx& c, int k, int j) {
+    const int s = j >= c.dr;
+    const int r = j - s * c.dr;
+    return c.br[((size_t)s * c.dm + k) * c.dr + r];
+  }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
+    c.theta[(size_t)i * (2 * c.dr) + j] = make_double2(re, im);
+  }
+};
+
+hipError_t launch_theta(const ThetaItem* items_dev, int items, int max_rows, int max_cols,
+                        hipStream_t s) {
+  ThetaP p{items_dev};
+  return launch_cgemm<64, 64, 16>(p, items, max_rows, max_cols, s);
+}
+
+// C^{t1 t2}_{l r} = sum_{s1 s2} Q[(t1 t2),(s1 s2)] Theta[(s1,l),(s2,r)]  (Eq. C)
+// W = lambda_l C                                                       (Eq. C~)
+// One thread per (l, r); ||W||_F^2 accumulated per item.
+__global__ __launch_bounds__(256) void mix_kernel(const MixItem* items, int per_item_blocks) {
+  const int item = blockIdx.x / per_item_blocks;
+  const int blk = blockIdx.x - item * per_item_blocks;
+  const MixItem it = items[item];
+  const int dl = it.dl, dr = it.dr;
+  const int idx = blk * 256 + threadIdx.x;
+  double local = 0.0;
+  if (idx < dl * dr) {
+    const int l = idx / dr, r = idx - (idx / dr) * dr;
+    const size_t ld = 2 * (size_t)dr;
+    double2 th[4];
+#pragma unroll
+    for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) th[s1 * 2 + s2] = it.c[(size_t)(s1 * dl + l) * ld + s2 * dr + r];
+    const double lam = it.lam[l];
+#pragma unroll
+    for (int t1 = 0; t1 < 2; ++t1)
+#pragma unroll
+      for (int t2 = 0; t2 < 2; ++t2) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 v = cmul(it.q[(t1 * 2 + t2) * 4 + k], th[k]);
+          acc.x += v.x;
+          acc.y += v.y;
+        }
+        const size_t o = (size_t)(t1 * dl + l) * ld + t2 * dr + r;
+        it.c[o] = acc;
+        const double2 wv = make_double2(lam * acc.x, lam * acc.y);
+        it.w[o] = wv;
+        local += wv.x * wv.x + wv.y * wv.y;
+      }
+  }
+  local = wave_sum(local);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(it.fro2, part[0] + part[1] + part[2] + part[3]);
+}
+
+hipError_t launch_mix(const MixItem* items_dev, int items, int max_dldr, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const int per = cdiv(max_dldr, 256);
+  hipLaunchKernelGGL(mix_kernel, dim3(items * per), dim3(256), 0, s, items_dev, per);
+  return hipGetLastError();
+}
+
+// =================================================================== Algorithm 1
+
+// Rotate local vectors i and j (one wave): b_ii, b_jj, b_ij by wave
+// reductions, then, if |b_ij| > eps sqrt(b_ii b_jj) and |b_ij| > floor,
+//   tau = (b_ii - b_jj) / (2|b_ij|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+//   c = 1/sqrt(1+t^2), s = t c, e = b_ij / |b_ij|,
+//   a_i <- c a_i + s conj(e) a_j,   a_j <- c a_j - s e a_i.
+__device__ __forceinline__ bool jacobi_pair(double2* xi, double2* xj, int m, int lane, double eps,
+                                            double floor) {
+  double bii = 0.0, bjj = 0.0, br = 0.0, bi = 0.0;
+  for (int e = lane; e < m; e += 64) {
+    const double2 a = xi[e], b = xj[e];
+    bii += a.x * a.x + a.y * a.y;
+    bjj += b.x * b.x + b.y * b.y;
+    br += a.x * b.x + a.y * b.y;
+    bi += a.x * b.y - a.y * b.x;
+  }
+  bii = wave_sum(bii);
+  bjj = wave_sum(bjj);
+  br = wave_sum(br);
+  bi = wave_sum(bi);
+  const double mag = sqrt(br * br + bi * bi);
+  if (!(mag > floor) || !(mag > eps * sqrt(bii * bjj))) return false;
+  const double tau = (bii - bjj) / (2.0 * mag);
+  const double at = fabs(tau);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  const double t = at > 1e100 ? sg * (0.5 / at) : sg / (at + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = t * c;
+  const double er = br / mag, ei = bi / mag;
+  for (int e = lane; e < m; e += 64) {
+    const double2 a = xi[e], b = xj[e];
+    // conj(e) b and e a
+    const double cbr = er * b.x + ei * b.y, cbi = er * b.y - ei * b.x;
+    const double ear = er * a.x - ei * a.y, eai = er * a.y + ei * a.x;
+    xi[e] = make_double2(c * a.x + s * cbr, c * a.y + s * cbi);
+    xj[e] = make_double2(c * b.x - s * ear, c * b.y - s * eai);
+  }
+  return true;
+}
+
+// One sweep over all pairs of the nloc local vectors in round-robin order
+// (nloc - 1 rounds of nloc/2 disjoint pairs, one pair per wave at a time).
+// gidx gives each local vector's global index (-1 = absent); pairs are
+// oriented so the lower global index plays the role of i.
+__device__ int jacobi_local_sweep(double2* sm, const int* gidx, int nloc, int m, double eps,
+                                  double floor, int* s_rot) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  if (threadIdx.x == 0) *s_rot = 0;
+  __syncthreads();
+  for (int ir = 0; ir < nloc - 1; ++ir) {
+    for (int pp = wave; pp < nloc / 2; pp += nwaves) {
+      int i = (pp == 0) ? 0 : 1 + ((pp - 1 + ir) % (nloc - 1));
+      int j = 1 + ((nloc - 2 - pp + ir) % (nloc - 1));
+      const int gi = gidx[i], gj = gidx[j];
+      if (gi < 0 || gj < 0) continue;
+      if (gi > gj) {
+        const int tmp = i;
+        i = j;
+        j = tmp;
+      }
+      if (jacobi_pair(sm + (size_t)i * m, sm + (size_t)j * m, m, lane, eps, floor) && lane == 0)
+        atomicAdd(s_rot, 1);
+    }
+    __syncthreads();
+  }
+  return *s_rot;
+}
+
+// Block mode: one workgroup per block pair of round `round`; the pair's
+// 2*wblk vectors are staged in LDS, swept once, and written back.
+__global__ __launch_bounds__(512) void jacobi_block_kernel(const JacItem* items, int max_pairs,
+                                                           int round, int sweep, double eps_scale) {
+  extern __shared__ double2 sm[];
+  __shared__ int gidx[256];
+  __shared__ int s_rot;
+  const int item = blockIdx.x / max_pairs;
+  const int p = blockIdx.x - item * max_pairs;
+  const JacItem it = items[item];
+  const int nb = it.nb;
+  if (p >= nb / 2 || round >= nb - 1) return;
+  if (sweep > 0 && it.rot[sweep - 1] == 0) return;  // converged in the previous sweep
+  const int w = it.wblk, m = it.m, n = it.n;
+  const int bp = (p == 0) ? 0 : 1 + ((p - 1 + round) % (nb - 1));
+  const int bq = 1 + ((nb - 2 - p + round) % (nb - 1));
+  const int nloc = 2 * w;
+  for (int lv = threadIdx.x; lv < nloc; lv += blockDim.x) {
+    const int g = lv < w ? bp * w + lv : bq * w + (lv - w);
+    gidx[lv] = g < n ? g : -1;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nloc * m; idx += blockDim.x) {
+    const int lv = idx / m;
+    const int e = idx - lv * m;
+    const int g = gidx[lv];
+    sm[idx] = g >= 0 ? it.w[(size_t)g * m + e] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double eps = eps_scale * (double)m;
+  const double floor = eps * eps * (*it.fro2);
+  const int rot = jacobi_local_sweep(sm, gidx, nloc, m, eps, floor, &s_rot);
+  if (rot > 0) {
+    for (int idx = threadIdx.x; idx < nloc * m; idx += blockDim.x) {
+      const int lv = idx / m;
+      const int e = idx - lv * m;
+      const int g = gidx[lv];
+      if (g >= 0) it.w[(size_t)g * m + e] = sm[idx];
+    }
+    if (threadIdx.x == 0) atomicAdd(&it.rot[sweep], rot);
+  }
+}
+
+// Single mode: the whole matrix fits in LDS; sweep until a sweep performs no
+// rotation or max_sweeps is reached.
+__global__ __launch_bounds__(512) void jacobi_single_kernel(const JacItem* items, int max_sweeps,
+                                                            double eps_scale) {
+  extern __shared__ double2 sm[];
+  __shared__ int gidx[1024];
+  __shared__ int s_rot;
+  const JacItem it = items[blockIdx.x];
+  const int n = it.n, m = it.m;
+  const int nloc = (n + 1) & ~1;
+  for (int lv = threadIdx.x; lv < nloc; lv += blockDim.x) gidx[lv] = lv < n ? lv : -1;
+  for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) sm[idx] = it.w[idx];
+  __syncthreads();
+  const double eps = eps_scale * (double)m;
+  const double floor = eps * eps * (*it.fro2);
+  int done = -max_sweeps;
+  int any = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    const int rot = jacobi_local_sweep(sm, gidx, nloc, m, eps, floor, &s_rot);
+    __syncthreads();
+    any += rot;
+    if (rot == 0) {
+      done = sw + 1;
+      break;
+    }
+  }
+  if (any > 0)
+    for (int idx = threadIdx.x; idx < n * m; idx += blockDim.x) it.w[idx] = sm[idx];
+  if (threadIdx.x == 0) *it.sweeps_done = done;
+}
+
+hipError_t configure_jacobi_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)jacobi_single_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_jacobi_block(const JacItem* items_dev, int items, int max_pairs, int round,
+                               int sweep, double eps_scale, size_t lds_bytes, hipStream_t s) {
+  if (items <= 0 || max_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_block_kernel, dim3(items * max_pairs), dim3(512), lds_bytes, s,
+                     items_dev, max_pairs, round, sweep, eps_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_single(const JacItem* items_dev, int items, int max_sweeps,
+                                double eps_scale, size_t lds_bytes, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_single_kernel, dim3(items), dim3(512), lds_bytes, s, items_dev,
+                     max_sweeps, eps_scale);
+  return hipGetLastError();
+}
+
+// sigma_i = ||a_i||, stable descending sort, k = min(cap, #{sigma > cutoff ||sigma||}) >= 1,
+// normalised output vectors (Algorithm 1's final loop and sort; truncation of Eq. svd).
+__global__ __launch_bounds__(1024) void finalize_kernel(const FinItem* items) {
+  __shared__ double sig[1024];
+  __shared__ int perm[1024];
+  __shared__ int s_k;
+  __shared__ double s_inv;
+  const FinItem it = items[blockIdx.x];
+  const int n = it.n, m = it.m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = wave; v < n; v += 16) {
+    double acc = 0.0;
+    for (int e = lane; e < m; e += 64) {
+      const double2 x = it.w[(size_t)v * m + e];
+      acc += x.x * x.x + x.y * x.y;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sig[v] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double si = sig[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = sig[j];
+      r += (sj > si) || (sj == si && j < i);
+    }
+    perm[r] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    bool bad = false;
+    for (int a = 0; a < n; ++a) {
+      const double sv = sig[perm[a]];
+      if (!isfinite(sv)) bad = true;
+      tot += sv * sv;
+    }
+    const double nrm = sqrt(tot);
+    int k = 0;
+    while (k < n && sig[perm[k]] > it.cutoff * nrm) ++k;
+    if (k < 1) k = 1;
+    if (k > it.cap) k = it.cap;
+    double kept2 = 0.0, disc2 = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double sv = sig[perm[a]];
+      if (a < k) kept2 += sv * sv;
+      else disc2 += sv * sv;
+    }
+    const double kept = sqrt(kept2);
+    if (bad || !(kept > 0.0) || !isfinite(kept)) {
+      *it.status_out = 1;
+      s_inv = 0.0;
+    } else {
+      *it.status_out = 0;
+      s_inv = 1.0 / kept;
+    }
+    *it.k_out = k;
+    *it.scale_out = s_inv;
+    *it.disc_out = tot > 0.0 ? disc2 / tot : 0.0;
+    s_k = k;
+  }
+  __syncthreads();
+  const int k = s_k;
+  const double inv = s_inv;
+  if (it.mode == FIN_LEFT) {
+    for (int idx = threadIdx.x; idx < m * k; idx += blockDim.x) {
+      const int e = idx / k, a = idx - (idx / k) * k;
+      const double sv = sig[perm[a]];
+      const double2 x = it.w[(size_t)perm[a] * m + e];
+      it.vec_out[idx] = sv > 0.0 ? make_double2(x.x / sv, x.y / sv) : make_double2(0.0, 0.0);
+    }
+  } else {
+    for (int a = threadIdx.x; a < k; a += blockDim.x) it.lam_out[a] = sig[perm[a]] * inv;
+    const int half = m / 2;
+    for (int idx = threadIdx.x; idx < k * m; idx += blockDim.x) {
+      const int a = idx / m, e = idx - (idx / m) * m;
+      const int s = e / half, r = e - s * half;
+      const double sv = sig[perm[a]];
+      const double2 x = it.w[(size_t)perm[a] * m + e];
+      it.vec_out[((size_t)s * k + a) * half + r] =
+          sv > 0.0 ? make_double2(x.x / sv, x.y / sv) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+hipError_t launch_finalize(const FinItem* items_dev, int items, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(items), dim3(1024), 0, s, items_dev);
+  return hipGetLastError();
+}
+
+// =================================================================== Eq. (Bl)
+
+struct TruncP {
+  using T = double;
+  using Ctx = TruncItem;
+  static constexpr bool A_CONTIG_K = true, B_CONTIG_N = false, REAL_ONLY = false;
+  const TruncItem* items;
+  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.rows;
+    N = c.k;
+    K = 2 * c.dr;
+  }
+  __device__ static double2 loadA(const Ctx& c, int i, int k) { return c.c[(size_t)i * (2 * c.dr) + k]; }
+  __device__ static double2 loadB(const Ctx& c, int k, int j) {
+    const int s = k >= c.dr;
+    const int r = k - s * c.dr;
+    const double2 v = c.v[((size_t)s * c.k + j) * c.dr + r];
+    return make_double2(v.x, -v.y);
+  }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
+    const double sc = *c.scale;
+    c.out[(size_t)i * c.k + j] = make_double2(re * sc, im * sc);
+  }
+};
+
+hipError_t launch_trunc(const TruncItem* items_dev, int items, int max_rows, int max_k,
+                        hipStream_t s) {
+  TruncP p{items_dev};
+  return launch_cgemm<64, 64, 16>(p, items, max_rows, max_k, s);
+}
+
+// =================================================================== canonical form
+
+struct CanonLeftP {  // W[beta][(s,alpha)] = sum_g B[s][g][beta] T[alpha][g]
+  using T = double;
+  using Ctx = CanonLeftItem;
+  static constexpr bool A_CONTIG_K = false, B_CONTIG_N = false, REAL_ONLY = false;
+  const CanonLeftItem* items;
+  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.db;
+    N = c.r;
+    K = c.dg;
+  }
+  __device__ static double2 loadA(const Ctx& c, int i, int k) {
+    return c.b[((size_t)c.s * c.dg + k) * c.db + i];
+  }
+  __device__ static double2 loadB(const Ctx& c, int k, int j) { return c.t[(size_t)j * c.dg + k]; }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
+    c.w[(size_t)i * (2 * c.r) + c.s * c.r + j] = make_double2(re, im);
+  }
+};
+
+struct CanonCarryLeftP {  // T'[a][beta] = sum_e conj(A[e][a]) W0[beta][e]
+  using T = double;
+  using Ctx = CanonCarryLeftItem;
+  static constexpr bool A_CONTIG_K = false, B_CONTIG_N = false, REAL_ONLY = false;
+  const CanonCarryLeftItem* items;
+  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.k;
+    N = c.db;
+    K = c.m;
+  }
+  __device__ static double2 loadA(const Ctx& c, int i, int k) {
+    const double2 v = c.a[(size_t)k * c.k + i];
+    return make_double2(v.x, -v.y);
+  }
+  __device__ static double2 loadB(const Ctx& c, int k, int j) { return c.w0[(size_t)j * c.m + k]; }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
+    c.t[(size_t)i * c.db + j] = make_double2(re, im);
+  }
+};
+
+struct CanonRightP {  // W[alpha][(s,b')] = sum_beta A[s][alpha][beta] T[beta][b']
+  using T = double;
+  using Ctx = CanonRightItem;
+  static constexpr bool A_CONTIG_K = true, B_CONTIG_N = true, REAL_ONLY = false;
+  const CanonRightItem* items;
+  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.dl;
+    N = c.r;
+    K = c.dm;
+  }
+  __device__ static double2 loadA(const Ctx& c, int i, int k) {
+    return c.a[((size_t)c.s * c.dl + i) * c.dm + k];
+  }
+  __device__ static double2 loadB(const Ctx& c, int k, int j) { return c.t[(size_t)k * c.r + j]; }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
+    c.w[(size_t)i * (2 * c.r) + c.s * c.r + j] = make_double2(re, im);
+  }
+};
+
+hipError_t launch_canon_left(const CanonLeftItem* items_dev, int items, int max_db, int max_r,
+                             hipStream_t s) {
+  CanonLeftP p{items_dev};
+  return launch_cgemm<64, 64, 16>(p, items, max_db, max_r, s);
+}
+hipError_t launch_canon_carry_left(const CanonCarryLeftItem* items_dev, int items, int max_k,
+                                   int max_db, hipStream_t s) {
+  CanonCarryLeftP p{items_dev};
+  return launch_cgemm<64, 64, 16>(p, items, max_k, max_db, s);
+}
+hipError_t launch_canon_right(const CanonRightItem* items_dev, int items, int max_dl, int max_r,
+                              hipStream_t s) {
+  CanonRightP p{items_dev};
+  return launch_cgemm<64, 64, 16>(p, items, max_dl, max_r, s);
+}
+
+__global__ __launch_bounds__(256) void fro2_kernel(const double2* w, int count, double* out) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+    const double2 x = w[i];
+    acc += x.x * x.x + x.y * x.y;
+  }
+  acc = wave_sum(acc);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+hipError_t launch_fro2(const double2* w, int count, double* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int blocks = cdiv(count, 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(fro2_kernel, dim3(blocks), dim3(256), 0, s, w, count, out);
+  return hipGetLastError();
+}
+
+__global__ void copy_kernel(double2* dst, const double2* src, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy(double2* dst, const double2* src, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, count);
+  return hipGetLastError();
+}
+
+__global__ void fill_ident_kernel(double2* dst, int d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < d * d) dst[i] = make_double2((i / d) == (i % d) ? 1.0 : 0.0, 0.0);
+}
+
+hipError_t launch_fill_ident(double2* dst, int d, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_ident_kernel, dim3(cdiv((long long)d * d, 256)), dim3(256), 0, s, dst, d);
+  return hipGetLastError();
+}
+
+// =================================================================== Eq. (expec2)
+
+// X = L [A^0 | A^1]: (Dl x Dl)(Dl x 2Dr); shared site A, one item per parent.
+template <typename TT>
+struct EnvG1P {
+  using T = TT;
+  using C2 = typename cplx_of<TT>::type;
+  struct Ctx {
+    const C2* l;
+    C2* x;
+    const C2* site;
+    int dl, dr;
+  };
+  static constexpr bool A_CONTIG_K = true, B_CONTIG_N = true, REAL_ONLY = false;
+  const EnvParent<C2>* items;
+  const C2* site;
+  int dl, dr;
+  __device__ Ctx context(int i) const {
+    const EnvParent<C2> e = items[i];
+    return Ctx{e.l, e.x, site, dl, dr};
+  }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.dl;
+    N = 2 * c.dr;
+    K = c.dl;
+  }
+  __device__ static C2 loadA(const Ctx& c, int i, int k) { return c.l[(size_t)i * c.dl + k]; }
+  __device__ static C2 loadB(const Ctx& c, int k, int j) {
+    const int s = j >= c.dr;
+    const int b = j - s * c.dr;
+    return c.site[((size_t)s * c.dl + k) * c.dr + b];
+  }
+  __device__ static void store(const Ctx& c, int i, int j, TT re, TT im) {
+    C2 v;
+    v.x = re;
+    v.y = im;
+    c.x[(size_t)i * (2 * c.dr) + j] = v;
+  }
+};
+
+// L' = sum_s A^{s+} Y^s with Y^s = sum_s' sigma_{ss'} X^{s'}: a block swap
+// (X, Y letters) and a phase (Y: -i, +i; Z: +1, -1) folded into the B fetch.
+template <typename TT>
+struct EnvG2P {
+  using T = TT;
+  using C2 = typename cplx_of<TT>::type;
+  struct Ctx {
+    const C2* x;
+    C2* out;
+    const C2* site;
+    int dl, dr, letter;
+  };
+  static constexpr bool A_CONTIG_K = false, B_CONTIG_N = true, REAL_ONLY = false;
+  const EnvChild<C2>* items;
+  const C2* site;
+  int dl, dr;
+  __device__ Ctx context(int i) const {
+    const EnvChild<C2> e = items[i];
+    return Ctx{e.x, e.out, site, dl, dr, e.letter};
+  }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.dr;
+    N = c.dr;
+    K = 2 * c.dl;
+  }
+  __device__ static C2 loadA(const Ctx& c, int i, int k) {
+    const int s = k >= c.dl;
+    const int a = k - s * c.dl;
+    C2 v = c.site[((size_t)s * c.dl + a) * c.dr + i];
+    v.y = -v.y;
+    return v;
+  }
+  __device__ static C2 loadB(const Ctx& c, int k, int j) {
+    const int s = k >= c.dl;
+    const int a = k - s * c.dl;
+    const int flip = (c.letter == 1 || c.letter == 2) ? 1 : 0;
+    const C2 v = c.x[(size_t)a * (2 * c.dr) + (s ^ flip) * c.dr + j];
+    C2 o = v;
+    if (c.letter == 2) {  // Y: s=0 -> -i X^1, s=1 -> +i X^0
+      if (s == 0) { o.x = v.y; o.y = -v.x; }
+      else { o.x = -v.y; o.y = v.x; }
+    } else if (c.letter == 3 && s == 1) {
+      o.x = -v.x;
+      o.y = -v.y;
+    }
+    return o;
+  }
+  __device__ static void store(const Ctx& c, int i, int j, TT re, TT im) {
+    C2 v;
+    v.x = re;
+    v.y = im;
+    c.out[(size_t)i * c.dr + j] = v;
+  }
+};
+
+hipError_t launch_env_gemm1_c128(const EnvParent<double2>* items, int count, const double2* site,
+                                 int dl, int dr, hipStream_t s) {
+  EnvG1P<double> p{items, site, dl, dr};
+  return launch_cgemm<64, 64, 16>(p, count, dl, 2 * dr, s);
+}
+hipError_t launch_env_gemm2_c128(const EnvChild<double2>* items, int count, const double2* site,
+                                 int dl, int dr, hipStream_t s) {
+  EnvG2P<double> p{items, site, dl, dr};
+  return launch_cgemm<64, 64, 16>(p, count, dr, dr, s);
+}
+hipError_t launch_env_gemm1_c64(const EnvParent<float2>* items, int count, const float2* site,
+                                int dl, int dr, hipStream_t s) {
+  EnvG1P<float> p{items, site, dl, dr};
+  return launch_cgemm<64, 64, 16>(p, count, dl, 2 * dr, s);
+}
+hipError_t launch_env_gemm2_c64(const EnvChild<float2>* items, int count, const float2* site,
+                                int dl, int dr, hipStream_t s) {
+  EnvG2P<float> p{items, site, dl, dr};
+  return launch_cgemm<64, 64, 16>(p, count, dr, dr, s);
+}
+
+// Site tensor in the environment precision (fwd, may be null) and its
+// per-letter transpose tr[s][beta][alpha] = B[s][alpha][beta], which turns the
+// right update R' = sum sigma B^{s'} R B^{s+} into the left form on R^T.
+template <typename C2>
+__global__ void site_prepare_kernel(const double2* site, C2* fwd, C2* tr, int dl, int dr) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int per = dl * dr;
+  if (idx >= 2 * per) return;
+  const int s = idx / per;
+  const int rem = idx - s * per;
+  const int a = rem / dr, b = rem - (rem / dr) * dr;
+  const double2 v = site[idx];
+  C2 o;
+  o.x = v.x;
+  o.y = v.y;
+  if (fwd) fwd[idx] = o;
+  tr[(size_t)s * per + (size_t)b * dl + a] = o;
+}
+
+hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr, int dl, int dr,
+                               int elem_bytes, hipStream_t s) {
+  const int blocks = cdiv(2LL * dl * dr, 256);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(site_prepare_kernel<double2>, dim3(blocks), dim3(256), 0, s, site,
+                       (double2*)out_fwd, (double2*)out_tr, dl, dr);
+  else
+    hipLaunchKernelGGL(site_prepare_kernel<float2>, dim3(blocks), dim3(256), 0, s, site,
+                       (float2*)out_fwd, (float2*)out_tr, dl, dr);
+  return hipGetLastError();
+}
+
+// Roots of the two tries at one bond: diag(lambda^2) (Eq. expec1/expec2) and
+// the identity (right boundary in right-canonical form, Eq. rc).
+template <typename C2>
+__global__ void roots_kernel(const double* lam, C2* lroot, C2* rroot, int d) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= d * d) return;
+  const int i = idx / d, j = idx - (idx / d) * d;
+  C2 z;
+  z.x = 0;
+  z.y = 0;
+  C2 lv = z, rv = z;
+  if (i == j) {
+    lv.x = lam[i] * lam[i];
+    rv.x = 1;
+  }
+  if (lroot) lroot[idx] = lv;
+  if (rroot) rroot[idx] = rv;
+}
+
+hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,
+                        hipStream_t s) {
+  const int blocks = cdiv((long long)d * d, 256);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(roots_kernel<double2>, dim3(blocks), dim3(256), 0, s, lam, (double2*)lroot,
+                       (double2*)rroot, d);
+  else
+    hipLaunchKernelGGL(roots_kernel<float2>, dim3(blocks), dim3(256), 0, s, lam, (float2*)lroot,
+                       (float2*)rroot, d);
+  return hipGetLastError();
+}
+
+// Closing traces: Tr(L_a R_b) = sum_{xy} L_a[x][y] R_b[y][x] = sum_x L_a[x] R^T_b[x]
+// with right environments stored transposed; computed in FP64 for every
+// (prefix, suffix) pair of a bond, real part only.
+template <typename C2>
+struct GramP {
+  using T = double;
+  using Ctx = GramItem;
+  static constexpr bool A_CONTIG_K = true, B_CONTIG_N = false, REAL_ONLY = true;
+  const GramItem* items;
+  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.nl;
+    N = c.nr;
+    K = c.kdim;
+  }
+  __device__ static double2 loadA(const Ctx& c, int i, int k) {
+    const C2 v = ((const C2*)c.lptr[i])[k];
+    return make_double2((double)v.x, (double)v.y);
+  }
+  __device__ static double2 loadB(const Ctx& c, int k, int j) {
+    const C2 v = ((const C2*)c.rptr[j])[k];
+    return make_double2((double)v.x, (double)v.y);
+  }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double) {
+    c.g[(size_t)i * c.nr + j] = re;
+  }
+};
+
+hipError_t launch_gram(const GramItem* items_dev, int items, int max_nl, int max_nr, int elem_bytes,
+                       hipStream_t s) {
+  if (elem_bytes == 16) {
+    GramP<double2> p{items_dev};
+    return launch_cgemm<64, 64, 16>(p, items, max_nl, max_nr, s);
+  }
+  GramP<float2> p{items_dev};
+  return launch_cgemm<64, 64, 16>(p, items, max_nl, max_nr, s);
+}
+
+__global__ void gather_kernel(const double* g, const int64_t* gidx, double* per_term, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i < n) per_term[i] = g[gidx[i]];
+}
+
+hipError_t launch_gather(const double* g, const int64_t* gidx, double* per_term, int64_t n,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, gidx,
+                     per_term, n);
+  return hipGetLastError();
+}
+
+// E = sum_k c_k <P_k>: each thread a contiguous chunk with error-free
+// transformations (TwoProduct by fma, TwoSum), then a fixed-shape tree of
+// double-double additions -- the result depends only on the string order.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__global__ __launch_bounds__(1024) void energy_kernel(const double* per_term, const double* coeffs,
+                                                      int64_t n, double* out) {
+  __shared__ double hs[1024], ls[1024];
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t lo = threadIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0, c = 0.0;
+  for (int64_t i = lo; i < hi; ++i) {
+    const double p = coeffs[i] * per_term[i];
+    const double pe = fma(coeffs[i], per_term[i], -p);
+    double t, e;
+    two_sum(s, p, t, e);
+    s = t;
+    c += e + pe;
+  }
+  hs[threadIdx.x] = s;
+  ls[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      double t, e;
+      two_sum(hs[threadIdx.x], hs[threadIdx.x + w], t, e);
+      hs[threadIdx.x] = t;
+      ls[threadIdx.x] = ls[threadIdx.x] + ls[threadIdx.x + w] + e;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = hs[0] + ls[0];
+}
+
+hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(1024), 0, s, per_term, coeffs, n, out);
+  return hipGetLastError();
+}
+
+// One 16x16x4 MFMA of known operands in FP64 (out[0..255]) and FP32
+// (out[256..511]), written back through the accumulator layout the GEMMs use.
+__global__ void selftest_mfma_kernel(double* out) {
+  const int l = threadIdx.x;
+  const int r = l & 15, k = l >> 4;
+  const double a = 1.0 + r + 0.5 * k;            // A[r][k]
+  const double b = 1.0 + 0.25 * k - 0.125 * r;   // B[k][r]
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  acc = mfma_16x16x4(a, b, acc);
+  f4_t facc = {0.f, 0.f, 0.f, 0.f};
+  facc = mfma_16x16x4((float)a, (float)b, facc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    out[acc_row<double>(k, v) * 16 + r] = acc[v];
+    out[256 + acc_row<float>(k, v) * 16 + r] = (double)facc[v];
+  }
+}
+
+hipError_t launch_selftest_mfma(double* out, hipStream_t s) {
+  hipLaunchKernelGGL(selftest_mfma_kernel, dim3(1), dim3(64), 0, s, out);
+  return hipGetLastError();
+}
+
+}  // namespace mps

@@ -1,0 +1,1377 @@
+// Host orchestration and the C ABI of the MPS energy evaluator.
+//
+// Every numerical step runs in the kernels of kernels.hip; this file owns the
+// device memory, builds the per-launch descriptors (checking every size
+// against the capacity of the buffer it addresses), sequences the launches on
+// the handle's stream and implements the error contract of include/mps.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+#include "mps.h"
+#include "planner.h"
+
+using namespace mps;
+
+namespace {
+
+thread_local std::string g_err;
+
+mps_status fail(mps_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+constexpr double kEpsScale = 1.1102230246251565e-16;  // 2^-53: eps = m * 2^-53 (Algorithm 1)
+constexpr double kCanonCutoff = 1e-14;                  // round-off singular values only
+constexpr int kDefaultSweeps = 30;
+constexpr int kMaxBond = 512;                           // finalize handles 2D <= 1024 vectors
+
+int cap_dim(int b, int n, int D) {
+  const int e = std::min(b, n - b);
+  if (e >= 30) return D;
+  return std::min(D, 1 << e);
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+size_t g_lds_budget = 0;  // dynamic LDS the Jacobi kernels may use
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// plan object
+
+struct mps_psum {
+  PauliPlan plan;
+  uint64_t serial;
+};
+
+static uint64_t g_plan_serial = 1;
+
+// ----------------------------------------------------------------------------
+// handle
+
+struct ExpectSetup {
+  uint64_t plan_serial = 0;
+  int prec = -1;
+  std::vector<int> dims;
+  // device storage
+  void* pool = nullptr;        // environments (left nodes, right nodes, roots)
+  size_t pool_bytes = 0;
+  void* sites = nullptr;       // prepared site tensors (fwd in env precision, transposed)
+  size_t sites_bytes = 0;
+  void* xbuf = nullptr;        // GEMM1 outputs for one chunk of parents
+  size_t xbuf_bytes = 0;
+  void* desc = nullptr;        // all descriptors
+  size_t desc_bytes = 0;
+  double* gbuf = nullptr;      // closing traces
+  size_t gbuf_count = 0;
+  double* per_term = nullptr;
+  double* coeffs = nullptr;
+  int64_t* gidx = nullptr;
+  double* energy = nullptr;
+  size_t terms_cap = 0;
+  // launch lists (host)
+  struct EnvLaunch {
+    int site, dl, dr;
+    size_t parents_off, children_off;  // byte offsets into desc
+    int n_parents, n_children;
+    bool left;                         // left pass (forward tensor) or right pass (transposed)
+    double flops;
+  };
+  std::vector<EnvLaunch> left_launches, right_launches;
+  struct PrepSite {
+    int dl, dr;
+    void* fwd;
+    void* tr;
+  };
+  std::vector<PrepSite> prep;
+  struct RootFill {
+    int bond, d;
+    void* lroot;
+    void* rroot;
+  };
+  std::vector<RootFill> roots;
+  size_t gram_off = 0;
+  int gram_items = 0, gram_max_nl = 0, gram_max_nr = 0;
+  double gram_flops = 0.0;
+  int64_t n_updates = 0;
+};
+
+struct mps_state {
+  int n = 0, D = 0, max_sweeps = kDefaultSweeps;
+  double cutoff = 0.0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, held = 0;
+  bool poisoned = false;
+  std::vector<int> dims, cap;
+  std::vector<double2*> site[2];
+  std::vector<int> site_cur;
+  std::vector<size_t> site_cap;  // complex elements
+  std::vector<double*> lam[2];
+  std::vector<int> lam_cur;
+  bool canonical = true;
+  double norm = 1.0;
+  double discarded = 0.0;
+  // device helpers
+  double2** d_site_ptrs = nullptr;
+  double** d_lam_ptrs = nullptr;
+  uint8_t* d_bits = nullptr;
+  double* d_one = nullptr;
+  // gate workspaces
+  int ws_items = 0;
+  size_t ws_stride = 0;  // complex elements per item
+  double2* ws_c = nullptr;
+  double2* ws_w = nullptr;
+  double* d_fro2 = nullptr;
+  int* d_rot = nullptr;
+  int* d_sweeps = nullptr;
+  int* d_k = nullptr;
+  double* d_scale = nullptr;
+  double* d_disc = nullptr;
+  int* d_status = nullptr;
+  double2* d_carry[2] = {nullptr, nullptr};
+  void* d_desc = nullptr;
+  size_t desc_bytes = 0;
+  double2* d_gates = nullptr;
+  size_t gates_cap = 0;
+  std::vector<std::pair<void*, size_t>> allocs;
+  ExpectSetup ex;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_env, ev_close;
+  size_t ev_env_used = 0, ev_close_used = 0;
+  mps_timing tm{};
+
+  double2* cur(int q) { return site[site_cur[q]][q]; }
+  double2* spare(int q) { return site[1 - site_cur[q]][q]; }
+  double* lcur(int b) { return lam[lam_cur[b]][b]; }
+  double* lspare(int b) { return lam[1 - lam_cur[b]][b]; }
+};
+
+namespace {
+
+mps_status dev_fail(mps_state* h, const char* what, hipError_t e) {
+  if (h) h->poisoned = true;
+  return fail(MPS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr)                                   \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return dev_fail((h), #expr, e_); \
+  } while (0)
+
+mps_status dalloc(mps_state* h, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (h->budget && h->held + bytes > h->budget)
+    return fail(MPS_ERR_BUDGET, "HBM budget exceeded: need " + std::to_string(h->held + bytes) +
+                                    " bytes, budget " + std::to_string(h->budget));
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(MPS_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  h->held += bytes;
+  h->allocs.emplace_back(*p, bytes);
+  return MPS_OK;
+}
+
+void dfree(mps_state* h, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < h->allocs.size(); ++i)
+    if (h->allocs[i].first == p) {
+      h->held -= h->allocs[i].second;
+      h->allocs.erase(h->allocs.begin() + i);
+      (void)hipFree(p);
+      return;
+    }
+}
+
+template <typename T>
+mps_status dalloc_t(mps_state* h, T** p, size_t count) {
+  void* v = nullptr;
+  mps_status st = dalloc(h, &v, count * sizeof(T));
+  *p = (T*)v;
+  return st;
+}
+
+mps_status check_handle(mps_state* h) {
+  if (!h) return fail(MPS_ERR_ARG, "NULL handle");
+  if (h->poisoned) return fail(MPS_ERR_DEVICE, "handle poisoned by an earlier device error");
+  return MPS_OK;
+}
+
+mps_status ensure_lds(mps_state* h) {
+  if (g_lds_budget) return MPS_OK;
+  int dev = 0, v = 0;
+  HIP_TRY(h, hipGetDevice(&dev));
+  HIP_TRY(h, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  size_t b = (size_t)v;
+  if (b > 160 * 1024) b = 160 * 1024;
+  b = b > 8 * 1024 ? b - 8 * 1024 : b;  // room for the kernels' static shared arrays
+  if (b > 128 * 1024) b = 128 * 1024;
+  HIP_TRY(h, configure_jacobi_lds(b));
+  g_lds_budget = b;
+  return MPS_OK;
+}
+
+// Descriptor upload: ordered after the stream's earlier work (which may still
+// read the region) and complete before returning, so the host source may be
+// a temporary.
+mps_status upload(mps_state* h, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return MPS_OK;
+  HIP_TRY(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return MPS_OK;
+}
+
+mps_status sync(mps_state* h) {
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return MPS_OK;
+}
+
+mps_status ensure_desc(mps_state* h, size_t bytes) {
+  if (bytes <= h->desc_bytes) return MPS_OK;
+  if (h->d_desc) {
+    mps_status st = sync(h);
+    if (st != MPS_OK) return st;
+    dfree(h, h->d_desc);
+    h->d_desc = nullptr;
+    h->desc_bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)1 << 16);
+  mps_status st = dalloc(h, &h->d_desc, want);
+  if (st != MPS_OK) return st;
+  h->desc_bytes = want;
+  return MPS_OK;
+}
+
+// Gate workspaces for up to `items` two-qubit gates at the handle's largest size.
+mps_status ensure_ws(mps_state* h, int items) {
+  if (items <= h->ws_items) return MPS_OK;
+  mps_status st = sync(h);
+  if (st != MPS_OK) return st;
+  for (void* p : {(void*)h->ws_c, (void*)h->ws_w, (void*)h->d_fro2, (void*)h->d_rot,
+                  (void*)h->d_sweeps, (void*)h->d_k, (void*)h->d_scale, (void*)h->d_disc,
+                  (void*)h->d_status})
+    dfree(h, p);
+  int dmax = 1;
+  for (int b = 0; b <= h->n; ++b) dmax = std::max(dmax, h->cap[b]);
+  h->ws_stride = (size_t)(2 * dmax) * (2 * dmax);
+  h->ws_items = 0;
+  if ((st = dalloc_t(h, &h->ws_c, h->ws_stride * items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->ws_w, h->ws_stride * items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_fro2, items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_rot, (size_t)items * h->max_sweeps)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_sweeps, items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_k, items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_scale, items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_disc, items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->d_status, items)) != MPS_OK) return st;
+  if (!h->d_carry[0]) {
+    for (int i = 0; i < 2; ++i)
+      if ((st = dalloc_t(h, &h->d_carry[i], (size_t)dmax * dmax)) != MPS_OK) return st;
+  }
+  h->ws_items = items;
+  return MPS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// batched one-sided Jacobi over items already described in host vectors
+
+struct JacobiPlanHost {
+  std::vector<JacItem> single, block;
+  size_t single_lds = 0, block_lds = 0;
+  int block_pairs = 0, block_rounds = 0;
+};
+
+void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
+  const size_t budget = g_lds_budget;
+  for (JacItem it : all) {
+    const size_t per_vec = (size_t)it.m * sizeof(double2);
+    const int max_vec = (int)std::max<size_t>(2, budget / per_vec);
+    const int nloc = (it.n + 1) & ~1;
+    if (nloc <= max_vec && nloc <= 1024) {
+      it.wblk = nloc;
+      it.nb = 1;
+      jp.single.push_back(it);
+      jp.single_lds = std::max(jp.single_lds, (size_t)it.n * per_vec);
+    } else {
+      int w = std::min(128, max_vec / 2);
+      if (w < 1) w = 1;
+      int nb = (it.n + w - 1) / w;
+      if (nb & 1) ++nb;
+      it.wblk = w;
+      it.nb = nb;
+      jp.block.push_back(it);
+      jp.block_lds = std::max(jp.block_lds, (size_t)(2 * w) * per_vec);
+      jp.block_pairs = std::max(jp.block_pairs, nb / 2);
+      jp.block_rounds = std::max(jp.block_rounds, nb - 1);
+    }
+  }
+}
+
+// Runs Algorithm 1 on every item (vectors in it.w, ||w||_F^2 in it.fro2 already
+// on device).  Requires item.rot zeroed for max_sweeps entries.  On return
+// (after a stream sync) `sweeps_out[i]` holds the sweeps used, or -1.
+mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc_off,
+                      std::vector<int>& sweeps_out) {
+  JacobiPlanHost jp;
+  plan_jacobi(all, jp);
+  const size_t bytes = (jp.single.size() + jp.block.size()) * sizeof(JacItem);
+  mps_status st = ensure_desc(h, desc_off + bytes);
+  if (st != MPS_OK) return st;
+  char* base = (char*)h->d_desc + desc_off;
+  JacItem* d_single = (JacItem*)base;
+  JacItem* d_block = d_single + jp.single.size();
+  std::vector<JacItem> both(jp.single);
+  both.insert(both.end(), jp.block.begin(), jp.block.end());
+  if ((st = upload(h, base, both.data(), bytes)) != MPS_OK) return st;
+  if (!jp.single.empty())
+    HIP_TRY(h, launch_jacobi_single(d_single, (int)jp.single.size(), h->max_sweeps, kEpsScale,
+                                    jp.single_lds, h->stream));
+  std::vector<int> block_sweeps(jp.block.size(), -1);
+  if (!jp.block.empty()) {
+    std::vector<int> rot(jp.block.size());
+    int done = 0;
+    for (int sw = 0; sw < h->max_sweeps && done < (int)jp.block.size(); ++sw) {
+      for (int r = 0; r < jp.block_rounds; ++r)
+        HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
+                                       kEpsScale, jp.block_lds, h->stream));
+      if (sw >= 3 || sw == h->max_sweeps - 1) {
+        for (size_t i = 0; i < jp.block.size(); ++i)
+          HIP_TRY(h, hipMemcpyAsync(&rot[i], jp.block[i].rot + sw, sizeof(int),
+                                    hipMemcpyDeviceToHost, h->stream));
+        if ((st = sync(h)) != MPS_OK) return st;
+        done = 0;
+        for (size_t i = 0; i < jp.block.size(); ++i) {
+          if (block_sweeps[i] < 0 && rot[i] == 0) block_sweeps[i] = sw + 1;
+          if (block_sweeps[i] >= 0) ++done;
+        }
+      }
+    }
+    // a sweep before the first check may already have been rotation-free
+    for (size_t i = 0; i < jp.block.size(); ++i) {
+      if (block_sweeps[i] >= 0) {
+        std::vector<int> r(block_sweeps[i]);
+        HIP_TRY(h, hipMemcpyAsync(r.data(), jp.block[i].rot, sizeof(int) * r.size(),
+                                  hipMemcpyDeviceToHost, h->stream));
+        if ((st = sync(h)) != MPS_OK) return st;
+        for (int s = 0; s < (int)r.size(); ++s)
+          if (r[s] == 0) {
+            block_sweeps[i] = s + 1;
+            break;
+          }
+      }
+    }
+  }
+  std::vector<int> single_sweeps(jp.single.size());
+  for (size_t i = 0; i < jp.single.size(); ++i)
+    HIP_TRY(h, hipMemcpyAsync(&single_sweeps[i], jp.single[i].sweeps_done, sizeof(int),
+                              hipMemcpyDeviceToHost, h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  // map back to the caller's order (items are identified by their w pointer)
+  sweeps_out.assign(all.size(), -1);
+  for (size_t i = 0; i < all.size(); ++i) {
+    for (size_t j = 0; j < jp.single.size(); ++j)
+      if (jp.single[j].w == all[i].w) sweeps_out[i] = single_sweeps[j] > 0 ? single_sweeps[j] : -1;
+    for (size_t j = 0; j < jp.block.size(); ++j)
+      if (jp.block[j].w == all[i].w) sweeps_out[i] = block_sweeps[j];
+  }
+  for (int s : sweeps_out)
+    if (s > 0) h->tm.jacobi_sweeps += s;
+  return MPS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// two-qubit gates (Eqs. C, C~, svd, Bl), one batch of disjoint bonds
+
+mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::vector<int>& gidx) {
+  const int items = (int)qs.size();
+  mps_status st = ensure_ws(h, items);
+  if (st != MPS_OK) return st;
+  std::vector<ThetaItem> th(items);
+  std::vector<MixItem> mx(items);
+  std::vector<JacItem> jc(items);
+  std::vector<FinItem> fn(items);
+  int max_rows = 0, max_cols = 0, max_dldr = 0;
+  for (int b = 0; b < items; ++b) {
+    const int q = qs[b];
+    const int dl = h->dims[q], dm = h->dims[q + 1], dr = h->dims[q + 2];
+    if ((size_t)(2 * dl) * (2 * dr) > h->ws_stride)
+      return fail(MPS_ERR_STATE, "internal: workspace too small");
+    double2* c = h->ws_c + (size_t)b * h->ws_stride;
+    double2* w = h->ws_w + (size_t)b * h->ws_stride;
+    th[b] = ThetaItem{h->cur(q), h->cur(q + 1), c, dl, dm, dr};
+    mx[b] = MixItem{c, w, h->lcur(q), h->d_gates + (size_t)gidx[b] * 16, h->d_fro2 + b, dl, dr};
+    jc[b] = JacItem{w, h->d_fro2 + b, h->d_rot + (size_t)b * h->max_sweeps, h->d_sweeps + b,
+                    2 * dl, 2 * dr, 0, 0};
+    const int capk = h->cap[q + 1];
+    fn[b] = FinItem{w, h->spare(q + 1), h->lspare(q + 1), h->d_k + b, h->d_scale + b,
+                    h->d_disc + b, h->d_status + b, 2 * dl, 2 * dr, capk, h->cutoff, FIN_GATE};
+    max_rows = std::max(max_rows, 2 * dl);
+    max_cols = std::max(max_cols, 2 * dr);
+    max_dldr = std::max(max_dldr, dl * dr);
+  }
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_th = place(sizeof(ThetaItem) * items);
+  const size_t o_mx = place(sizeof(MixItem) * items);
+  const size_t o_fn = place(sizeof(FinItem) * items);
+  const size_t o_tr = place(sizeof(TruncItem) * items);
+  const size_t o_jac = off;
+  if ((st = ensure_desc(h, off + 2 * sizeof(JacItem) * items + 512)) != MPS_OK) return st;
+  char* d = (char*)h->d_desc;
+  if ((st = upload(h, d + o_th, th.data(), sizeof(ThetaItem) * items)) != MPS_OK) return st;
+  if ((st = upload(h, d + o_mx, mx.data(), sizeof(MixItem) * items)) != MPS_OK) return st;
+  if ((st = upload(h, d + o_fn, fn.data(), sizeof(FinItem) * items)) != MPS_OK) return st;
+  HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double) * items, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * items * h->max_sweeps, h->stream));
+  HIP_TRY(h, launch_theta((const ThetaItem*)(d + o_th), items, max_rows, max_cols, h->stream));
+  HIP_TRY(h, launch_mix((const MixItem*)(d + o_mx), items, max_dldr, h->stream));
+  std::vector<int> sweeps;
+  if ((st = run_jacobi(h, jc, o_jac, sweeps)) != MPS_OK) return st;
+  HIP_TRY(h, launch_finalize((const FinItem*)(d + o_fn), items, h->stream));
+  std::vector<int> k(items), status(items);
+  std::vector<double> disc(items);
+  HIP_TRY(h, hipMemcpyAsync(k.data(), h->d_k, sizeof(int) * items, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(status.data(), h->d_status, sizeof(int) * items,
+                            hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(disc.data(), h->d_disc, sizeof(double) * items,
+                            hipMemcpyDeviceToHost, h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  for (int b = 0; b < items; ++b) {
+    if (sweeps[b] < 0)
+      return fail(MPS_ERR_NOCONV, "Jacobi SVD did not converge within " +
+                                      std::to_string(h->max_sweeps) + " sweeps (gate on qubit " +
+                                      std::to_string(qs[b]) + ")");
+    if (status[b] != 0)
+      return fail(MPS_ERR_NONFINITE, "non-finite or zero singular values (gate on qubit " +
+                                         std::to_string(qs[b]) + ")");
+    if (k[b] < 1 || k[b] > h->cap[qs[b] + 1])
+      return fail(MPS_ERR_STATE, "internal: kept rank out of range");
+  }
+  std::vector<TruncItem> tr(items);
+  int max_k = 0;
+  for (int b = 0; b < items; ++b) {
+    const int q = qs[b];
+    tr[b] = TruncItem{h->ws_c + (size_t)b * h->ws_stride, h->spare(q + 1), h->spare(q),
+                      h->d_scale + b, 2 * h->dims[q], h->dims[q + 2], k[b]};
+    max_k = std::max(max_k, k[b]);
+  }
+  if ((st = upload(h, d + o_tr, tr.data(), sizeof(TruncItem) * items)) != MPS_OK) return st;
+  HIP_TRY(h, launch_trunc((const TruncItem*)(d + o_tr), items, max_rows, max_k, h->stream));
+  for (int b = 0; b < items; ++b) {
+    const int q = qs[b];
+    h->site_cur[q] ^= 1;
+    h->site_cur[q + 1] ^= 1;
+    h->lam_cur[q + 1] ^= 1;
+    h->dims[q + 1] = k[b];
+    h->discarded += disc[b];
+  }
+  h->canonical = false;
+  return MPS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// canonical form: left-to-right orthonormalisation, right-to-left SVD sweep
+
+mps_status canonicalize_impl(mps_state* h) {
+  const double t0 = now_ms();
+  mps_status st = ensure_ws(h, 1);
+  if (st != MPS_OK) return st;
+  const int n = h->n;
+  const double2 one = make_double2(1.0, 0.0);
+  double2* T = h->d_carry[0];
+  double2* Tn = h->d_carry[1];
+  if ((st = upload(h, T, &one, sizeof(double2))) != MPS_OK) return st;
+  double2* W0 = h->ws_c;
+  double2* W = h->ws_w;
+  char* d = nullptr;
+  std::vector<int> sweeps;
+  int r = 1;  // rows of the carry
+  // ---- left to right: M = T B_q (2r x Db); U of its SVD becomes A_q, carry U^+ M
+  const std::vector<int> od = h->dims;  // shapes of the B tensors before the sweep
+  for (int q = 0; q < n; ++q) {
+    const int dg = od[q], db = od[q + 1];
+    const int m = 2 * r;
+    if ((size_t)db * m > h->ws_stride) return fail(MPS_ERR_STATE, "internal: canon workspace");
+    CanonLeftItem cl[2] = {{h->cur(q), T, W0, r, dg, db, 0}, {h->cur(q), T, W0, r, dg, db, 1}};
+    FinItem fi{W, h->spare(q), nullptr, h->d_k, h->d_scale, h->d_disc, h->d_status,
+               db, m, h->cap[q + 1], kCanonCutoff, FIN_LEFT};
+    if ((st = ensure_desc(h, 4096)) != MPS_OK) return st;
+    d = (char*)h->d_desc;
+    if ((st = upload(h, d, cl, sizeof(cl))) != MPS_OK) return st;
+    if ((st = upload(h, d + 512, &fi, sizeof(fi))) != MPS_OK) return st;
+    HIP_TRY(h, launch_canon_left((const CanonLeftItem*)d, 2, db, r, h->stream));
+    HIP_TRY(h, launch_copy(W, W0, (size_t)db * m, h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double), h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * h->max_sweeps, h->stream));
+    HIP_TRY(h, launch_fro2(W, db * m, h->d_fro2, h->stream));
+    std::vector<JacItem> jc{JacItem{W, h->d_fro2, h->d_rot, h->d_sweeps, db, m, 0, 0}};
+    if ((st = run_jacobi(h, jc, 1024, sweeps)) != MPS_OK) return st;
+    if (sweeps[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi did not converge in canonicalisation");
+    HIP_TRY(h, launch_finalize((const FinItem*)(d + 512), 1, h->stream));
+    int k = 0, status = 0;
+    HIP_TRY(h, hipMemcpyAsync(&k, h->d_k, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&status, h->d_status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    if ((st = sync(h)) != MPS_OK) return st;
+    if (status != 0) return fail(MPS_ERR_NONFINITE, "non-finite state in canonicalisation");
+    CanonCarryLeftItem cc{h->spare(q), W0, Tn, k, m, db};
+    if ((st = upload(h, d + 2048, &cc, sizeof(cc))) != MPS_OK) return st;
+    HIP_TRY(h, launch_canon_carry_left((const CanonCarryLeftItem*)(d + 2048), 1, k, db, h->stream));
+    h->site_cur[q] ^= 1;  // A_q (2, r, k) is now the site tensor
+    h->dims[q + 1] = k;
+    std::swap(T, Tn);
+    r = k;
+  }
+  // T is the 1x1 carry (norm and phase); A_{n-1} has right bond 1.
+  // ---- right to left: M = A_q T (Dl x 2r'); B_q = normalised rows of V^+, lambda_q = sigma
+  int rr = 1;
+  const std::vector<int> od2 = h->dims;  // shapes of the A tensors after the first sweep
+  for (int q = n - 1; q >= 0; --q) {
+    const int dl = od2[q], dm = od2[q + 1];
+    const int m = 2 * rr;
+    if ((size_t)dl * m > h->ws_stride) return fail(MPS_ERR_STATE, "internal: canon workspace");
+    CanonRightItem cr[2] = {{h->cur(q), T, W0, dl, dm, rr, 0}, {h->cur(q), T, W0, dl, dm, rr, 1}};
+    FinItem fi{W, h->spare(q), h->lspare(q), h->d_k, h->d_scale, h->d_disc, h->d_status,
+               dl, m, h->cap[q], kCanonCutoff, FIN_RIGHT};
+    d = (char*)h->d_desc;
+    if ((st = upload(h, d, cr, sizeof(cr))) != MPS_OK) return st;
+    if ((st = upload(h, d + 512, &fi, sizeof(fi))) != MPS_OK) return st;
+    HIP_TRY(h, launch_canon_right((const CanonRightItem*)d, 2, dl, rr, h->stream));
+    HIP_TRY(h, launch_copy(W, W0, (size_t)dl * m, h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double), h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * h->max_sweeps, h->stream));
+    HIP_TRY(h, launch_fro2(W, dl * m, h->d_fro2, h->stream));
+    std::vector<JacItem> jc{JacItem{W, h->d_fro2, h->d_rot, h->d_sweeps, dl, m, 0, 0}};
+    if ((st = run_jacobi(h, jc, 1024, sweeps)) != MPS_OK) return st;
+    if (sweeps[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi did not converge in canonicalisation");
+    HIP_TRY(h, launch_finalize((const FinItem*)(d + 512), 1, h->stream));
+    int k = 0, status = 0;
+    double scale = 0.0;
+    HIP_TRY(h, hipMemcpyAsync(&k, h->d_k, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&status, h->d_status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&scale, h->d_scale, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if ((st = sync(h)) != MPS_OK) return st;
+    if (status != 0) return fail(MPS_ERR_NONFINITE, "non-finite state in canonicalisation");
+    if (q > 0) {
+      TruncItem ti{W0, h->spare(q), Tn, h->d_one, dl, rr, k};
+      if ((st = upload(h, d + 2048, &ti, sizeof(ti))) != MPS_OK) return st;
+      HIP_TRY(h, launch_trunc((const TruncItem*)(d + 2048), 1, dl, k, h->stream));
+    } else {
+      h->norm = scale > 0.0 ? 1.0 / scale : 0.0;
+    }
+    h->site_cur[q] ^= 1;
+    h->lam_cur[q] ^= 1;
+    h->dims[q] = k;
+    std::swap(T, Tn);
+    rr = k;
+  }
+  if ((st = sync(h)) != MPS_OK) return st;
+  h->canonical = true;
+  h->tm.canon_ms += now_ms() - t0;
+  return MPS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// expectation values
+
+mps_status timed_begin(mps_state* h, std::vector<hipEvent_t>& pool, size_t& used, hipEvent_t& b,
+                       hipEvent_t& e) {
+  if (used + 2 > pool.size()) {
+    const size_t grow = std::max<size_t>(64, pool.size());
+    for (size_t i = 0; i < grow; ++i) {
+      hipEvent_t ev;
+      HIP_TRY(h, hipEventCreate(&ev));
+      pool.push_back(ev);
+    }
+  }
+  b = pool[used];
+  e = pool[used + 1];
+  used += 2;
+  HIP_TRY(h, hipEventRecord(b, h->stream));
+  return MPS_OK;
+}
+
+mps_status flush_timing(mps_state* h) {
+  if (!h->timing) return MPS_OK;
+  mps_status st = sync(h);
+  if (st != MPS_OK) return st;
+  for (size_t i = 0; i + 1 < h->ev_env_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_env[i], h->ev_env[i + 1]));
+    h->tm.env_ms += ms;
+  }
+  for (size_t i = 0; i + 1 < h->ev_close_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_close[i], h->ev_close[i + 1]));
+    h->tm.close_ms += ms;
+  }
+  h->ev_env_used = h->ev_close_used = 0;
+  return MPS_OK;
+}
+
+mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
+  ExpectSetup& ex = h->ex;
+  const PauliPlan& P = ps->plan;
+  const int n = h->n;
+  if (ex.plan_serial == ps->serial && ex.prec == prec && ex.dims == h->dims) return MPS_OK;
+  mps_status st = sync(h);
+  if (st != MPS_OK) return st;
+  const size_t el = prec == MPS_PREC_C128 ? sizeof(double2) : sizeof(float2);
+  const std::vector<int>& D = h->dims;
+  // ---- environment pool layout
+  std::vector<size_t> loff(P.left.size()), roff(P.right.size());
+  size_t pool = 0;
+  for (size_t i = 0; i < P.left.size(); ++i) {
+    loff[i] = pool;
+    const size_t d = D[P.left[i].site + 1];
+    pool += d * d;
+  }
+  for (size_t i = 0; i < P.right.size(); ++i) {
+    roff[i] = pool;
+    const size_t d = D[P.right[i].site];
+    pool += d * d;
+  }
+  std::vector<char> need_l(n + 1, 0), need_r(n + 1, 0);
+  for (const TrieNode& nd : P.left)
+    if (is_root(nd.parent)) need_l[root_bond(nd.parent)] = 1;
+  for (const TrieNode& nd : P.right)
+    if (is_root(nd.parent)) need_r[root_bond(nd.parent)] = 1;
+  for (int64_t k = 0; k < P.n_terms; ++k) {
+    if (is_root(P.close_left[k])) need_l[root_bond(P.close_left[k])] = 1;
+    if (is_root(P.close_right[k])) need_r[root_bond(P.close_right[k])] = 1;
+  }
+  std::vector<size_t> lroot(n + 1, SIZE_MAX), rroot(n + 1, SIZE_MAX);
+  for (int b = 0; b <= n; ++b) {
+    const size_t d = D[b];
+    if (need_l[b]) { lroot[b] = pool; pool += d * d; }
+    if (need_r[b]) { rroot[b] = pool; pool += d * d; }
+  }
+  // ---- prepared sites
+  size_t site_elems = 0;
+  std::vector<size_t> sfwd(n), str(n);
+  for (int q = 0; q < n; ++q) {
+    const size_t cnt = 2 * (size_t)D[q] * D[q + 1];
+    sfwd[q] = site_elems;
+    if (el != sizeof(double2)) site_elems += cnt;
+    str[q] = site_elems;
+    site_elems += cnt;
+  }
+  // ---- X chunking
+  size_t xmax_per = 1;
+  for (int q = 0; q < n; ++q) {
+    xmax_per = std::max(xmax_per, (size_t)D[q] * 2 * D[q + 1]);
+    xmax_per = std::max(xmax_per, (size_t)D[q + 1] * 2 * D[q]);
+  }
+  const size_t x_budget_elems = std::max(xmax_per, ((size_t)1 << 30) / el);  // ~1 GiB
+  const int chunk_cap = (int)std::max<size_t>(1, x_budget_elems / xmax_per);
+  // ---- allocate (re-use when large enough)
+  auto grow = [&](void** p, size_t& have, size_t want) -> mps_status {
+    if (want <= have && *p) return MPS_OK;
+    dfree(h, *p);
+    *p = nullptr;
+    have = 0;
+    mps_status s2 = dalloc(h, p, want);
+    if (s2 == MPS_OK) have = want;
+    return s2;
+  };
+  if ((st = grow(&ex.pool, ex.pool_bytes, pool * el)) != MPS_OK) return st;
+  if ((st = grow(&ex.sites, ex.sites_bytes, site_elems * el)) != MPS_OK) return st;
+  const size_t x_elems = std::min<size_t>(x_budget_elems, xmax_per * (size_t)chunk_cap);
+  if ((st = grow(&ex.xbuf, ex.xbuf_bytes, x_elems * el)) != MPS_OK) return st;
+  char* poolp = (char*)ex.pool;
+  char* sitep = (char*)ex.sites;
+  auto lref_ptr = [&](int32_t ref) -> char* {
+    return is_root(ref) ? poolp + lroot[root_bond(ref)] * el : poolp + loff[ref] * el;
+  };
+  auto rref_ptr = [&](int32_t ref) -> char* {
+    return is_root(ref) ? poolp + rroot[root_bond(ref)] * el : poolp + roff[ref] * el;
+  };
+  // ---- descriptors
+  std::vector<char> host;
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t o = host.size();
+    host.resize(o + ((bytes + 255) & ~(size_t)255));
+    if (bytes && src) std::memcpy(host.data() + o, src, bytes);
+    return o;
+  };
+  ex.prep.clear();
+  for (int q = 0; q < n; ++q)
+    ex.prep.push_back({D[q], D[q + 1], el == sizeof(double2) ? nullptr : (void*)(sitep + sfwd[q] * el),
+                       (void*)(sitep + str[q] * el)});
+  ex.roots.clear();
+  for (int b = 0; b <= n; ++b)
+    if (need_l[b] || need_r[b])
+      ex.roots.push_back({b, D[b], need_l[b] ? (void*)(poolp + lroot[b] * el) : nullptr,
+                          need_r[b] ? (void*)(poolp + rroot[b] * el) : nullptr});
+  ex.n_updates = (int64_t)(P.left.size() + P.right.size());
+  auto build_pass = [&](const std::vector<TrieNode>& nodes, const std::vector<size_t>& off,
+                        bool left, std::vector<ExpectSetup::EnvLaunch>& out) {
+    out.clear();
+    size_t i = 0;
+    while (i < nodes.size()) {
+      const int site = nodes[i].site;
+      size_t j = i;
+      while (j < nodes.size() && nodes[j].site == site) ++j;
+      // left: parent at bond site (Dl = D[site]) -> child at bond site+1
+      // right (transposed form): parent at bond site+1 -> child at bond site
+      const int dl = left ? D[site] : D[site + 1];
+      const int dr = left ? D[site + 1] : D[site];
+      const size_t xper = (size_t)dl * 2 * dr;
+      size_t a = i;
+      while (a < j) {
+        // one chunk: up to chunk_cap distinct parents
+        std::vector<EnvParent<double2>> par;   // pointers only, reinterpreted per precision
+        std::vector<EnvChild<double2>> chi;
+        size_t b = a;
+        int32_t last_parent = INT32_MIN;
+        while (b < j) {
+          if (nodes[b].parent != last_parent) {
+            if ((int)par.size() == chunk_cap) break;
+            last_parent = nodes[b].parent;
+            char* pp = left ? lref_ptr(last_parent) : rref_ptr(last_parent);
+            par.push_back({(const double2*)pp, (double2*)((char*)ex.xbuf + par.size() * xper * el)});
+          }
+          chi.push_back({(const double2*)par.back().x, (double2*)(poolp + off[b] * el),
+                         (int)nodes[b].letter});
+          ++b;
+        }
+        ExpectSetup::EnvLaunch L;
+        L.site = site;
+        L.dl = dl;
+        L.dr = dr;
+        L.n_parents = (int)par.size();
+        L.n_children = (int)chi.size();
+        L.parents_off = put(par.data(), par.size() * sizeof(par[0]));
+        L.children_off = put(chi.data(), chi.size() * sizeof(chi[0]));
+        L.left = left;
+        L.flops = 8.0 * dl * dl * 2.0 * dr * par.size() + 8.0 * dr * dr * 2.0 * dl * chi.size();
+        out.push_back(L);
+        a = b;
+      }
+      i = j;
+    }
+  };
+  build_pass(P.left, loff, true, ex.left_launches);
+  build_pass(P.right, roff, false, ex.right_launches);
+  // ---- closes: per bond, unique left and right references
+  std::vector<std::vector<int64_t>> by_bond(n + 1);
+  for (int64_t k = 0; k < P.n_terms; ++k) by_bond[P.close_bond[k]].push_back(k);
+  std::vector<GramItem> gram;
+  std::vector<int64_t> gidx((size_t)P.n_terms);
+  size_t gtot = 0;
+  std::vector<std::vector<const void*>> lptrs, rptrs;
+  ex.gram_flops = 0.0;
+  ex.gram_max_nl = ex.gram_max_nr = 0;
+  for (int c = 0; c <= n; ++c) {
+    if (by_bond[c].empty()) continue;
+    std::unordered_map<int32_t, int> li, ri;
+    std::vector<const void*> lp, rp;
+    for (int64_t k : by_bond[c]) {
+      if (li.emplace(P.close_left[k], (int)lp.size()).second) lp.push_back(lref_ptr(P.close_left[k]));
+      if (ri.emplace(P.close_right[k], (int)rp.size()).second) rp.push_back(rref_ptr(P.close_right[k]));
+    }
+    for (int64_t k : by_bond[c])
+      gidx[k] = (int64_t)gtot + (int64_t)li[P.close_left[k]] * (int64_t)rp.size() + ri[P.close_right[k]];
+    GramItem gi{nullptr, nullptr, (double*)(uintptr_t)gtot, (int)lp.size(), (int)rp.size(),
+                D[c] * D[c]};
+    gram.push_back(gi);
+    lptrs.push_back(std::move(lp));
+    rptrs.push_back(std::move(rp));
+    gtot += (size_t)gi.nl * gi.nr;
+    ex.gram_flops += 4.0 * gi.nl * gi.nr * (double)gi.kdim;
+    ex.gram_max_nl = std::max(ex.gram_max_nl, gi.nl);
+    ex.gram_max_nr = std::max(ex.gram_max_nr, gi.nr);
+  }
+  if (gtot > ex.gbuf_count || !ex.gbuf) {
+    dfree(h, ex.gbuf);
+    ex.gbuf = nullptr;
+    if ((st = dalloc_t(h, &ex.gbuf, std::max<size_t>(gtot, 1))) != MPS_OK) return st;
+    ex.gbuf_count = gtot;
+  }
+  // pointer lists go into the descriptor blob; patch addresses after upload placement
+  std::vector<size_t> lp_off(gram.size()), rp_off(gram.size());
+  for (size_t g = 0; g < gram.size(); ++g) {
+    lp_off[g] = put(lptrs[g].data(), lptrs[g].size() * sizeof(void*));
+    rp_off[g] = put(rptrs[g].data(), rptrs[g].size() * sizeof(void*));
+  }
+  ex.gram_items = (int)gram.size();
+  ex.gram_off = put(nullptr, gram.size() * sizeof(GramItem));
+  // terms
+  const size_t T = (size_t)P.n_terms;
+  if (T > ex.terms_cap || !ex.per_term) {
+    for (void* p : {(void*)ex.per_term, (void*)ex.coeffs, (void*)ex.gidx, (void*)ex.energy})
+      dfree(h, p);
+    ex.per_term = ex.coeffs = ex.energy = nullptr;
+    ex.gidx = nullptr;
+    const size_t tc = std::max<size_t>(T, 1);
+    if ((st = dalloc_t(h, &ex.per_term, tc)) != MPS_OK) return st;
+    if ((st = dalloc_t(h, &ex.coeffs, tc)) != MPS_OK) return st;
+    if ((st = dalloc_t(h, &ex.gidx, tc)) != MPS_OK) return st;
+    if ((st = dalloc_t(h, &ex.energy, 1)) != MPS_OK) return st;
+    ex.terms_cap = tc;
+  }
+  // ---- upload the blob
+  if (host.size() > ex.desc_bytes || !ex.desc) {
+    dfree(h, ex.desc);
+    ex.desc = nullptr;
+    ex.desc_bytes = 0;
+    if ((st = dalloc(h, &ex.desc, host.size() + 256)) != MPS_OK) return st;
+    ex.desc_bytes = host.size() + 256;
+  }
+  char* db = (char*)ex.desc;
+  for (size_t g = 0; g < gram.size(); ++g) {
+    gram[g].lptr = (const void* const*)(db + lp_off[g]);
+    gram[g].rptr = (const void* const*)(db + rp_off[g]);
+    gram[g].g = ex.gbuf + (size_t)(uintptr_t)gram[g].g;
+  }
+  if (!gram.empty()) std::memcpy(host.data() + ex.gram_off, gram.data(), gram.size() * sizeof(GramItem));
+  HIP_TRY(h, hipMemcpy(ex.desc, host.data(), host.size(), hipMemcpyHostToDevice));
+  if (T) {
+    HIP_TRY(h, hipMemcpy(ex.gidx, gidx.data(), T * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(ex.coeffs, P.coeffs.data(), T * sizeof(double), hipMemcpyHostToDevice));
+  }
+  ex.plan_serial = ps->serial;
+  ex.prec = prec;
+  ex.dims = D;
+  return MPS_OK;
+}
+
+mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int prec) {
+  const char* db = (const char*)h->ex.desc;
+  // resolved per call: the live site buffer flips with every gate
+  const void* site_ptr = L.left ? (prec == MPS_PREC_C128 ? (const void*)h->cur(L.site)
+                                                         : h->ex.prep[L.site].fwd)
+                                : h->ex.prep[L.site].tr;
+  hipEvent_t b = nullptr, e = nullptr;
+  mps_status st;
+  if (h->timing && (st = timed_begin(h, h->ev_env, h->ev_env_used, b, e)) != MPS_OK) return st;
+  if (prec == MPS_PREC_C128) {
+    HIP_TRY(h, launch_env_gemm1_c128((const EnvParent<double2>*)(db + L.parents_off), L.n_parents,
+                                     (const double2*)site_ptr, L.dl, L.dr, h->stream));
+    HIP_TRY(h, launch_env_gemm2_c128((const EnvChild<double2>*)(db + L.children_off), L.n_children,
+                                     (const double2*)site_ptr, L.dl, L.dr, h->stream));
+  } else {
+    HIP_TRY(h, launch_env_gemm1_c64((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
+                                    (const float2*)site_ptr, L.dl, L.dr, h->stream));
+    HIP_TRY(h, launch_env_gemm2_c64((const EnvChild<float2>*)(db + L.children_off), L.n_children,
+                                    (const float2*)site_ptr, L.dl, L.dr, h->stream));
+  }
+  if (h->timing) {
+    HIP_TRY(h, hipEventRecord(e, h->stream));
+    h->tm.env_launches += 2;
+    h->tm.env_flops += L.flops;
+  }
+  return MPS_OK;
+}
+
+mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
+                       double* per_term) {
+  mps_status st;
+  if (!h->canonical && (st = canonicalize_impl(h)) != MPS_OK) return st;
+  const double t0 = now_ms();
+  if ((st = build_expect(h, ps, prec)) != MPS_OK) return st;
+  ExpectSetup& ex = h->ex;
+  const int el = prec == MPS_PREC_C128 ? 16 : 8;
+  // layer 0: site tensors in environment precision and transposed; trie roots
+  for (int q = 0; q < h->n; ++q)
+    HIP_TRY(h, launch_site_prepare(h->cur(q), ex.prep[q].fwd, ex.prep[q].tr, ex.prep[q].dl,
+                                   ex.prep[q].dr, el, h->stream));
+  for (const auto& r : ex.roots)
+    HIP_TRY(h, launch_roots(h->lcur(r.bond), r.lroot, r.rroot, r.d, el, h->stream));
+  for (const auto& L : ex.left_launches)
+    if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
+  for (const auto& L : ex.right_launches)
+    if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
+  hipEvent_t b = nullptr, e = nullptr;
+  if (h->timing && (st = timed_begin(h, h->ev_close, h->ev_close_used, b, e)) != MPS_OK) return st;
+  HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off), ex.gram_items,
+                         ex.gram_max_nl, ex.gram_max_nr, el, h->stream));
+  if (h->timing) {
+    HIP_TRY(h, hipEventRecord(e, h->stream));
+    h->tm.close_flops += ex.gram_flops;
+    h->tm.env_updates += ex.n_updates;
+  }
+  const int64_t T = ps->plan.n_terms;
+  HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, ex.per_term, T, h->stream));
+  HIP_TRY(h, launch_energy(ex.per_term, ex.coeffs, T, ex.energy, h->stream));
+  double E = 0.0;
+  HIP_TRY(h, hipMemcpyAsync(&E, ex.energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (per_term && T)
+    HIP_TRY(h, hipMemcpyAsync(per_term, ex.per_term, sizeof(double) * T, hipMemcpyDeviceToHost,
+                              h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  if ((st = flush_timing(h)) != MPS_OK) return st;
+  *energy = E;
+  h->tm.expect_ms += now_ms() - t0;
+  return MPS_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" {
+
+const char* mps_last_error(void) { return g_err.c_str(); }
+
+mps_status mps_create(const mps_config* cfg, mps_handle* out) {
+  if (!cfg || !out) return fail(MPS_ERR_ARG, "NULL config or output");
+  if (cfg->n_qubits < 1 || cfg->n_qubits > 30000) return fail(MPS_ERR_ARG, "n_qubits out of range");
+  if (cfg->max_bond < 1 || cfg->max_bond > kMaxBond)
+    return fail(MPS_ERR_ARG, "max_bond must be in [1, 512]");
+  if (!(cfg->svd_cutoff >= 0.0) || !std::isfinite(cfg->svd_cutoff))
+    return fail(MPS_ERR_ARG, "svd_cutoff must be finite and >= 0");
+  if (cfg->max_jacobi_sweeps < 0 || cfg->max_jacobi_sweeps > 1000)
+    return fail(MPS_ERR_ARG, "max_jacobi_sweeps must be in [0, 1000]");
+  if (cfg->init_bits)
+    for (int q = 0; q < cfg->n_qubits; ++q)
+      if (cfg->init_bits[q] > 1) return fail(MPS_ERR_ARG, "init_bits must be 0 or 1");
+  struct Owner {
+    mps_state* p;
+    ~Owner() {
+      if (p) mps_destroy(p);
+    }
+    mps_state* get() const { return p; }
+    mps_state* operator->() const { return p; }
+    mps_state* release() {
+      mps_state* q = p;
+      p = nullptr;
+      return q;
+    }
+  } h{new mps_state()};
+  h->n = cfg->n_qubits;
+  h->D = cfg->max_bond;
+  h->cutoff = cfg->svd_cutoff;
+  h->max_sweeps = cfg->max_jacobi_sweeps ? cfg->max_jacobi_sweeps : kDefaultSweeps;
+  h->budget = cfg->hbm_budget_bytes;
+  if (cfg->stream) {
+    h->stream = (hipStream_t)cfg->stream;
+  } else {
+    HIP_TRY(nullptr, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    h->own_stream = true;
+  }
+  mps_status st = ensure_lds(h.get());
+  if (st != MPS_OK) return st;
+  const int n = h->n;
+  h->dims.assign(n + 1, 1);
+  h->cap.resize(n + 1);
+  for (int b = 0; b <= n; ++b) h->cap[b] = cap_dim(b, n, h->D);
+  for (int i = 0; i < 2; ++i) {
+    h->site[i].assign(n, nullptr);
+    h->lam[i].assign(n + 1, nullptr);
+  }
+  h->site_cur.assign(n, 0);
+  h->lam_cur.assign(n + 1, 0);
+  h->site_cap.resize(n);
+  for (int q = 0; q < n; ++q) {
+    h->site_cap[q] = 2 * (size_t)h->cap[q] * h->cap[q + 1];
+    for (int i = 0; i < 2; ++i)
+      if ((st = dalloc_t(h.get(), &h->site[i][q], h->site_cap[q])) != MPS_OK) return st;
+  }
+  for (int b = 0; b <= n; ++b)
+    for (int i = 0; i < 2; ++i)
+      if ((st = dalloc_t(h.get(), &h->lam[i][b], h->cap[b])) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_site_ptrs, n)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_lam_ptrs, n + 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_bits, n)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_one, 1)) != MPS_OK) return st;
+  const double one = 1.0;
+  HIP_TRY(h.get(), hipMemcpy(h->d_one, &one, sizeof(double), hipMemcpyHostToDevice));
+  if ((st = mps_reset(h.get(), cfg->init_bits)) != MPS_OK) return st;
+  *out = h.release();
+  return MPS_OK;
+}
+
+mps_status mps_destroy(mps_handle h) {
+  if (!h) return MPS_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& a : h->allocs) (void)hipFree(a.first);
+  for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_close) (void)hipEventDestroy(e);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return MPS_OK;
+}
+
+mps_status mps_reset(mps_handle h, const uint8_t* bits) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  const int n = h->n;
+  std::vector<uint8_t> b(n, 0);
+  if (bits)
+    for (int q = 0; q < n; ++q) {
+      if (bits[q] > 1) return fail(MPS_ERR_ARG, "bits must be 0 or 1");
+      b[q] = bits[q];
+    }
+  std::fill(h->site_cur.begin(), h->site_cur.end(), 0);
+  std::fill(h->lam_cur.begin(), h->lam_cur.end(), 0);
+  std::fill(h->dims.begin(), h->dims.end(), 1);
+  std::vector<double2*> sp(h->site[0]);
+  std::vector<double*> lp(h->lam[0]);
+  HIP_TRY(h, hipMemcpyAsync(h->d_site_ptrs, sp.data(), sizeof(double2*) * n, hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->d_lam_ptrs, lp.data(), sizeof(double*) * (n + 1),
+                            hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->d_bits, b.data(), n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, launch_init_product(h->d_site_ptrs, h->d_lam_ptrs, h->d_bits, n, h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  h->canonical = true;
+  h->norm = 1.0;
+  h->discarded = 0.0;
+  return MPS_OK;
+}
+
+mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const int32_t* q1,
+                           const double* u, int64_t* n_done) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (n_done) *n_done = 0;
+  if (ng < 0 || (ng > 0 && (!q0 || !q1 || !u))) return fail(MPS_ERR_ARG, "bad gate arrays");
+  for (int64_t i = 0; i < ng; ++i) {
+    if (q0[i] < 0 || q0[i] >= h->n) return fail(MPS_ERR_ARG, "gate " + std::to_string(i) + ": q0 out of range");
+    if (q1[i] >= 0 && (q1[i] != q0[i] + 1 || q1[i] >= h->n))
+      return fail(MPS_ERR_ARG, "gate " + std::to_string(i) + ": two-qubit gates must act on (q, q+1)");
+    if (!finite_all(u + 32 * i, q1[i] >= 0 ? 32 : 8))
+      return fail(MPS_ERR_NONFINITE, "gate " + std::to_string(i) + ": non-finite matrix entry");
+  }
+  const double t0 = now_ms();
+  const int64_t chunk = 1 << 16;
+  int64_t done = 0;
+  for (int64_t c0 = 0; c0 < ng; c0 += chunk) {
+    const int64_t c1 = std::min(ng, c0 + chunk);
+    const size_t need = (size_t)(c1 - c0) * 16;
+    if (need > h->gates_cap) {
+      if ((st = sync(h)) != MPS_OK) return st;
+      dfree(h, h->d_gates);
+      h->d_gates = nullptr;
+      h->gates_cap = 0;
+      if ((st = dalloc_t(h, &h->d_gates, need)) != MPS_OK) return st;
+      h->gates_cap = need;
+    }
+    if ((st = sync(h)) != MPS_OK) return st;
+    HIP_TRY(h, hipMemcpy(h->d_gates, u + 32 * c0, sizeof(double) * 32 * (c1 - c0),
+                         hipMemcpyHostToDevice));
+    int64_t i = c0;
+    while (i < c1) {
+      if (q1[i] < 0) {
+        const int q = q0[i];
+        HIP_TRY(h, launch_gate1q(h->cur(q), h->d_gates + (size_t)(i - c0) * 16,
+                                 h->dims[q] * h->dims[q + 1], h->stream));
+        h->canonical = false;
+        ++i;
+        done = i;
+        continue;
+      }
+      std::vector<int> qs, gi;
+      std::vector<char> used(h->n, 0);
+      int64_t j = i;
+      while (j < c1 && q1[j] >= 0 && !used[q0[j]] && !used[q0[j] + 1] && (int)qs.size() < h->n) {
+        used[q0[j]] = used[q0[j] + 1] = 1;
+        qs.push_back(q0[j]);
+        gi.push_back((int)(j - c0));
+        ++j;
+      }
+      if ((st = apply_2q_batch(h, qs, gi)) != MPS_OK) {
+        if (n_done) *n_done = done;
+        h->tm.gates_ms += now_ms() - t0;
+        return st;
+      }
+      i = j;
+      done = i;
+    }
+  }
+  if ((st = sync(h)) != MPS_OK) return st;
+  if (n_done) *n_done = done;
+  h->tm.gates_ms += now_ms() - t0;
+  return MPS_OK;
+}
+
+mps_status mps_apply_gate(mps_handle h, int32_t q0, int32_t q1, const double* u) {
+  if (!u) return fail(MPS_ERR_ARG, "NULL gate matrix");
+  double buf[32] = {0};
+  std::memcpy(buf, u, sizeof(double) * (q1 >= 0 ? 32 : 8));
+  return mps_apply_gates(h, 1, &q0, &q1, buf, nullptr);
+}
+
+mps_status mps_canonicalize(mps_handle h) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  return canonicalize_impl(h);
+}
+
+mps_status mps_norm(mps_handle h, double* norm) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!norm) return fail(MPS_ERR_ARG, "NULL output");
+  *norm = h->norm;
+  return MPS_OK;
+}
+
+mps_status mps_discarded_weight(mps_handle h, double* w) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!w) return fail(MPS_ERR_ARG, "NULL output");
+  *w = h->discarded;
+  return MPS_OK;
+}
+
+mps_status mps_bond_dims(mps_handle h, int32_t* dims) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!dims) return fail(MPS_ERR_ARG, "NULL output");
+  for (int b = 0; b <= h->n; ++b) dims[b] = h->dims[b];
+  return MPS_OK;
+}
+
+mps_status mps_pauli_sum_create(int32_t n_qubits, int64_t n_terms, const uint8_t* codes,
+                                const double* coeffs, mps_pauli_sum* out) {
+  if (!out) return fail(MPS_ERR_ARG, "NULL output");
+  std::unique_ptr<mps_psum> p(new mps_psum());
+  std::string err;
+  if (!build_pauli_plan(n_qubits, n_terms, codes, coeffs, p->plan, err))
+    return fail(MPS_ERR_ARG, err);
+  p->serial = g_plan_serial++;
+  *out = p.release();
+  return MPS_OK;
+}
+
+mps_status mps_pauli_sum_destroy(mps_pauli_sum p) {
+  delete p;
+  return MPS_OK;
+}
+
+mps_status mps_pauli_sum_stats(mps_pauli_sum p, int64_t* nl, int64_t* nr, int64_t* nc,
+                               int32_t* meet) {
+  if (!p) return fail(MPS_ERR_ARG, "NULL plan");
+  if (nl) *nl = (int64_t)p->plan.left.size();
+  if (nr) *nr = (int64_t)p->plan.right.size();
+  if (nc) *nc = p->plan.n_terms;
+  if (meet) *meet = p->plan.meet;
+  return MPS_OK;
+}
+
+mps_status mps_pauli_sum_export(mps_pauli_sum p, int32_t* lp, int32_t* ls, int32_t* ll,
+                                int32_t* rp, int32_t* rs, int32_t* rl, int32_t* cb, int32_t* cl,
+                                int32_t* cr) {
+  if (!p) return fail(MPS_ERR_ARG, "NULL plan");
+  const PauliPlan& P = p->plan;
+  for (size_t i = 0; i < P.left.size(); ++i) {
+    if (lp) lp[i] = P.left[i].parent;
+    if (ls) ls[i] = P.left[i].site;
+    if (ll) ll[i] = P.left[i].letter;
+  }
+  for (size_t i = 0; i < P.right.size(); ++i) {
+    if (rp) rp[i] = P.right[i].parent;
+    if (rs) rs[i] = P.right[i].site;
+    if (rl) rl[i] = P.right[i].letter;
+  }
+  for (int64_t k = 0; k < P.n_terms; ++k) {
+    if (cb) cb[k] = P.close_bond[k];
+    if (cl) cl[k] = P.close_left[k];
+    if (cr) cr[k] = P.close_right[k];
+  }
+  return MPS_OK;
+}
+
+mps_status mps_expect_pauli_sum(mps_handle h, mps_pauli_sum p, mps_precision prec, double* energy,
+                                double* per_term) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!p || !energy) return fail(MPS_ERR_ARG, "NULL plan or output");
+  if (p->plan.n_qubits != h->n) return fail(MPS_ERR_ARG, "plan and MPS qubit counts differ");
+  if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64)
+    return fail(MPS_ERR_ARG, "precision not available (c128 and c64 are implemented)");
+  return expect_impl(h, p, (int)prec, energy, per_term);
+}
+
+mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
+                           double* lambda_left) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (q < 0 || q >= h->n || !dl || !dr) return fail(MPS_ERR_ARG, "bad site or NULL outputs");
+  if ((st = sync(h)) != MPS_OK) return st;
+  const int a = h->dims[q], c = h->dims[q + 1];
+  if (b) HIP_TRY(h, hipMemcpy(b, h->cur(q), sizeof(double2) * 2 * a * c, hipMemcpyDeviceToHost));
+  if (lambda_left) HIP_TRY(h, hipMemcpy(lambda_left, h->lcur(q), sizeof(double) * a, hipMemcpyDeviceToHost));
+  *dl = a;
+  *dr = c;
+  return MPS_OK;
+}
+
+mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, const double* b,
+                           const double* lambda_left) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (q < 0 || q >= h->n || !b || !lambda_left) return fail(MPS_ERR_ARG, "bad site or NULL inputs");
+  if (dl < 1 || dr < 1 || dl > h->cap[q] || dr > h->cap[q + 1])
+    return fail(MPS_ERR_ARG, "site dimensions exceed the bond capacity");
+  if ((q == 0 && dl != 1) || (q == h->n - 1 && dr != 1))
+    return fail(MPS_ERR_ARG, "boundary bonds must have dimension 1");
+  if (!finite_all(b, 4 * (size_t)dl * dr) || !finite_all(lambda_left, dl))
+    return fail(MPS_ERR_NONFINITE, "non-finite import");
+  if ((st = sync(h)) != MPS_OK) return st;
+  HIP_TRY(h, hipMemcpy(h->cur(q), b, sizeof(double2) * 2 * dl * dr, hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->lcur(q), lambda_left, sizeof(double) * dl, hipMemcpyHostToDevice));
+  h->dims[q] = dl;
+  h->dims[q + 1] = dr;
+  h->canonical = true;
+  return MPS_OK;
+}
+
+mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors, double* sigma,
+                          double* out_vectors, int32_t* sweeps) {
+  if (n_vec < 1 || n_vec > 1024 || vec_len < 1 || vec_len > 4096 || !vectors || !sigma)
+    return fail(MPS_ERR_ARG, "need 1 <= n_vec <= 1024, 1 <= vec_len <= 4096 and non-NULL arrays");
+  if (!finite_all(vectors, 2 * (size_t)n_vec * vec_len))
+    return fail(MPS_ERR_NONFINITE, "non-finite input");
+  mps_state tmp;
+  tmp.n = 1;
+  HIP_TRY(nullptr, hipStreamCreateWithFlags(&tmp.stream, hipStreamNonBlocking));
+  tmp.own_stream = true;
+  struct Guard {
+    mps_state* s;
+    ~Guard() {
+      if (s->stream) (void)hipStreamSynchronize(s->stream);
+      for (auto& a : s->allocs) (void)hipFree(a.first);
+      if (s->stream) (void)hipStreamDestroy(s->stream);
+      s->allocs.clear();
+      s->stream = nullptr;
+    }
+  } guard{&tmp};
+  mps_state* h = &tmp;
+  mps_status st = ensure_lds(h);
+  if (st != MPS_OK) return st;
+  const size_t cnt = (size_t)n_vec * vec_len;
+  double2 *w = nullptr, *out = nullptr;
+  double *fro2 = nullptr, *lam = nullptr, *scale = nullptr, *disc = nullptr;
+  int *rot = nullptr, *sw = nullptr, *k = nullptr, *status = nullptr;
+  // FIN_GATE writes vec_out as [s][a][r] with m split in halves; with an odd
+  // length use FIN_LEFT-free path: pad the length to even.
+  const int m = vec_len + (vec_len & 1);
+  if ((st = dalloc_t(h, &w, (size_t)n_vec * m)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &out, (size_t)n_vec * m)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &fro2, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &lam, n_vec)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &scale, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &disc, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &rot, kDefaultSweeps * 2)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &sw, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &k, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &status, 1)) != MPS_OK) return st;
+  h->max_sweeps = kDefaultSweeps * 2;
+  std::vector<double2> padded((size_t)n_vec * m, make_double2(0.0, 0.0));
+  for (int v = 0; v < n_vec; ++v)
+    for (int e = 0; e < vec_len; ++e)
+      padded[(size_t)v * m + e] = make_double2(vectors[2 * ((size_t)v * vec_len + e)],
+                                               vectors[2 * ((size_t)v * vec_len + e) + 1]);
+  HIP_TRY(h, hipMemcpy(w, padded.data(), sizeof(double2) * padded.size(), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemset(fro2, 0, sizeof(double)));
+  HIP_TRY(h, hipMemset(rot, 0, sizeof(int) * h->max_sweeps));
+  HIP_TRY(h, launch_fro2(w, n_vec * m, fro2, h->stream));
+  std::vector<int> swp;
+  std::vector<JacItem> jc{JacItem{w, fro2, rot, sw, n_vec, m, 0, 0}};
+  if ((st = run_jacobi(h, jc, 0, swp)) != MPS_OK) return st;
+  if (swp[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi SVD did not converge");
+  FinItem fi{w, out, lam, k, scale, disc, status, n_vec, m, n_vec, 0.0, FIN_GATE};
+  if ((st = ensure_desc(h, 4096)) != MPS_OK) return st;
+  if ((st = upload(h, h->d_desc, &fi, sizeof(fi))) != MPS_OK) return st;
+  HIP_TRY(h, launch_finalize((const FinItem*)h->d_desc, 1, h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  int kk = 0, stt = 0;
+  double sc = 0.0;
+  HIP_TRY(h, hipMemcpy(&kk, k, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&stt, status, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&sc, scale, sizeof(double), hipMemcpyDeviceToHost));
+  // sigma: lam holds sigma / ||sigma|| for the kept (= all, cutoff 0) values
+  std::vector<double> lv(n_vec, 0.0);
+  HIP_TRY(h, hipMemcpy(lv.data(), lam, sizeof(double) * kk, hipMemcpyDeviceToHost));
+  for (int a = 0; a < n_vec; ++a) sigma[a] = (a < kk && sc > 0.0) ? lv[a] / sc : 0.0;
+  if (out_vectors) {
+    std::vector<double2> o((size_t)kk * m);
+    HIP_TRY(h, hipMemcpy(o.data(), out, sizeof(double2) * o.size(), hipMemcpyDeviceToHost));
+    const int half = m / 2;
+    std::memset(out_vectors, 0, sizeof(double) * 2 * cnt);
+    for (int a = 0; a < kk; ++a)
+      for (int e = 0; e < vec_len; ++e) {
+        const int s = e / half, r = e - s * half;
+        const double2 x = o[((size_t)s * kk + a) * half + r];
+        out_vectors[2 * ((size_t)a * vec_len + e)] = x.x;
+        out_vectors[2 * ((size_t)a * vec_len + e) + 1] = x.y;
+      }
+  }
+  if (sweeps) *sweeps = swp[0];
+  return MPS_OK;
+}
+
+mps_status mps_set_timing(mps_handle h, int32_t enabled) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if ((st = sync(h)) != MPS_OK) return st;
+  h->timing = enabled != 0;
+  h->tm = mps_timing{};
+  h->ev_env_used = h->ev_close_used = 0;
+  return MPS_OK;
+}
+
+mps_status mps_get_timing(mps_handle h, mps_timing* out) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!out) return fail(MPS_ERR_ARG, "NULL output");
+  if ((st = flush_timing(h)) != MPS_OK) return st;
+  *out = h->tm;
+  return MPS_OK;
+}
+
+mps_status mps_device_bytes(mps_handle h, size_t* bytes) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!bytes) return fail(MPS_ERR_ARG, "NULL output");
+  *bytes = h->held;
+  return MPS_OK;
+}
+
+mps_status mps_selftest_mfma(double* out) {
+  if (!out) return fail(MPS_ERR_ARG, "NULL output");
+  double* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, 512 * sizeof(double));
+  if (e != hipSuccess) return fail(MPS_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = launch_selftest_mfma(d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, d, 512 * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(MPS_ERR_DEVICE, std::string("selftest: ") + hipGetErrorString(e));
+  return MPS_OK;
+}
+
+}  // extern "C"

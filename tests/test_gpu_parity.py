@@ -1,0 +1,242 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+identical seeded inputs.  Tolerances: c128 energies within 1e-9 of the
+oracle (absolute, Hartree), per-string values within 1e-10; c64 energies
+within 1e-6 (derived in the design doc from FP32 rounding over the transfer
+chains); singular values within 1e-12 relative to the largest."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import MpsOracle, dense_apply_gates, dense_energy, dense_expect_pauli, \
+    dense_product_state
+from workloads import brickwork_gates, build_config, fuse_gates, hf_bits, jw_hamiltonian, \
+    pack_gates, random_integrals, workload_rng
+from workloads.circuits import gate_cnot
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _mps_state_from_gpu(m, n):
+    """Contract the exported site tensors into a statevector (test-side numpy)."""
+    psi = np.ones((1, 1), dtype=complex)
+    for q in range(n):
+        B, _ = m.export_site(q)
+        psi = np.einsum("pa,sab->psb", psi, B).reshape(-1, B.shape[2])
+    return psi.reshape((2,) * n)
+
+
+def _apply(m, gates):
+    q0, q1, u = pack_gates(gates)
+    assert m.apply_gates(q0, q1, u) == len(gates)
+
+
+def test_mfma_layout(gpu_lib):
+    from paper_2303_03681_amd import binding
+    out = binding.selftest_mfma()
+    r = np.arange(16)[:, None]
+    k = np.arange(4)[None, :]
+    A = 1.0 + r + 0.5 * k
+    B = 1.0 + 0.25 * np.arange(4)[:, None] - 0.125 * np.arange(16)[None, :]
+    assert np.max(np.abs(out[0] - A @ B)) < 1e-12
+    assert np.max(np.abs(out[1] - A @ B)) < 1e-4
+
+
+@pytest.mark.parametrize("n,m", [(4, 6), (16, 16), (33, 20), (64, 64), (20, 300), (96, 512),
+                                 (200, 64), (512, 512)])
+def test_jacobi_svd_matches_lapack(gpu_lib, n, m):
+    from paper_2303_03681_amd import binding
+    _say(f"jacobi n={n} m={m}")
+    r = np.random.default_rng(n * 1000 + m)
+    A = r.normal(size=(n, m)) + 1j * r.normal(size=(n, m))
+    sig, W, sweeps = binding.jacobi_svd(A)
+    ref = np.linalg.svd(A, compute_uv=False)
+    k = min(n, m)
+    assert np.max(np.abs(sig[:k] - ref)) < 1e-12 * ref[0]
+    assert np.all(sig[k:] < 1e-12 * ref[0])
+    Wk = W[:k]
+    assert np.max(np.abs(Wk @ Wk.conj().T - np.eye(k))) < 1e-12
+    # every row of A lies in the span of the kept right singular vectors
+    assert np.max(np.abs(A - (A @ Wk.conj().T) @ Wk)) < 1e-11 * ref[0]
+    assert 1 <= sweeps <= 30
+
+
+def test_c1_uccsd_end_to_end_vs_statevector(gpu_lib):
+    from paper_2303_03681_amd import binding
+    w = build_config(1)
+    _say(f"C1: {len(w.gates)} gates, {w.psum.n_terms} strings")
+    psi = dense_apply_gates(dense_product_state(w.bits), w.gates)
+    e_ref = dense_energy(psi, w.psum.codes, w.psum.coeffs)
+    m = binding.Mps(w.n_qubits, 16, 1e-14, bits=w.bits)
+    _apply(m, w.gates)
+    assert np.max(np.abs(_mps_state_from_gpu(m, w.n_qubits) - psi)) < 1e-11
+    ps = binding.PauliSum(w.psum.codes, w.psum.coeffs)
+    e, per = m.expect(ps, "c128", per_term=True)
+    assert abs(e - e_ref) < 1e-10
+    per_ref = np.array([dense_expect_pauli(psi, c).real for c in w.psum.codes])
+    assert np.max(np.abs(per - per_ref)) < 1e-11
+    assert abs(m.norm() - 1) < 1e-12
+    assert list(m.bond_dims()) == [1, 2, 4, 8, 16, 8, 4, 2, 1]
+    e64 = m.expect(ps, "c64")
+    assert abs(e64 - e_ref) < 1e-5
+
+
+def test_c1_canonicalize_preserves_state(gpu_lib):
+    from paper_2303_03681_amd import binding
+    w = build_config(1)
+    psi = dense_apply_gates(dense_product_state(w.bits), w.gates)
+    m = binding.Mps(w.n_qubits, 16, 1e-14, bits=w.bits)
+    _apply(m, w.gates)
+    m.canonicalize()
+    phi = _mps_state_from_gpu(m, w.n_qubits)
+    ov = np.vdot(phi, psi)
+    assert abs(abs(ov) - 1) < 1e-11, ov
+    assert np.max(np.abs(phi * (ov / abs(ov)) - psi)) < 1e-11
+    for q in range(w.n_qubits):
+        B, lam = m.export_site(q)
+        g = np.einsum("sab,scb->ac", B, B.conj())
+        assert np.max(np.abs(g - np.eye(g.shape[0]))) < 1e-12, q
+        s = np.linalg.svd(psi.reshape(1 << q, -1), compute_uv=False)[:lam.size]
+        assert np.max(np.abs(s - lam)) < 1e-12, q
+
+
+def test_c1_unfused_gates_exercise_one_qubit_kernel(gpu_lib):
+    from paper_2303_03681_amd import binding
+    w = build_config(1, fuse=False)
+    assert any(g.q1 < 0 for g in w.gates)
+    psi = dense_apply_gates(dense_product_state(w.bits), w.gates)
+    m = binding.Mps(w.n_qubits, 16, 1e-14, bits=w.bits)
+    _apply(m, w.gates)
+    assert np.max(np.abs(_mps_state_from_gpu(m, w.n_qubits) - psi)) < 1e-11
+
+
+@pytest.mark.parametrize("n_s,layers,D", [(5, 6, 8), (6, 5, 12), (7, 4, 32)])
+def test_truncated_brickwork_vs_oracle(gpu_lib, n_s, layers, D):
+    from paper_2303_03681_amd import binding
+    n = 2 * n_s
+    _say(f"brickwork n={n} layers={layers} D={D}")
+    h, g = random_integrals(n_s, workload_rng(60 + n_s, 0))
+    ps = jw_hamiltonian(h, g)
+    ang = workload_rng(60 + n_s, 1).uniform(-np.pi, np.pi, size=(layers, n, 2))
+    gates = fuse_gates(brickwork_gates(n, ang), n)
+    bits = hf_bits(n, n_s)
+    o = MpsOracle(n, D, 1e-14, bits)
+    o.apply_gates(gates)
+    m = binding.Mps(n, D, 1e-14, bits=bits)
+    _apply(m, gates)
+    assert list(m.bond_dims()) == o.bond_dims()
+    assert abs(m.discarded_weight() - o.discarded) < 1e-10 * max(1.0, o.discarded)
+    o.canonicalize()
+    plan = binding.PauliSum(ps.codes, ps.coeffs)
+    e, per = m.expect(plan, "c128", per_term=True)
+    ref = o.expect_terms(ps.codes).real
+    assert np.max(np.abs(per - ref)) < 1e-10
+    assert abs(e - math.fsum(ps.coeffs * ref)) < 1e-9
+    assert abs(m.norm() - o.norm_before_canon) < 1e-10
+    e64 = m.expect(plan, "c64")
+    assert abs(e64 - e) < 1e-5
+
+
+def _canonical_random_oracle(n, D, seed, layers=None):
+    """A canonical oracle MPS with saturated bonds from a brickwork circuit."""
+    ang = np.random.default_rng(seed).uniform(-np.pi, np.pi, size=(layers or n, n, 2))
+    o = MpsOracle(n, D, 1e-14, hf_bits(n, n // 2))
+    o.apply_gates(fuse_gates(brickwork_gates(n, ang), n))
+    o.canonicalize()
+    return o
+
+
+def test_imported_state_expectations(gpu_lib):
+    from paper_2303_03681_amd import binding
+    n, D = 12, 24
+    o = _canonical_random_oracle(n, D, 5, layers=6)
+    m = binding.Mps(n, D, 1e-14)
+    for q in range(n):
+        m.import_site(q, o.B[q], o.lam[q])
+    r = np.random.default_rng(7)
+    codes = r.integers(0, 4, size=(300, n)).astype(np.uint8)
+    codes[::7] = 0
+    codes[1::7, :n - 2] = 0
+    coeffs = r.normal(size=300)
+    plan = binding.PauliSum(codes, coeffs)
+    e, per = m.expect(plan, "c128", per_term=True)
+    ref = o.expect_terms(codes).real
+    assert np.max(np.abs(per - ref)) < 1e-11
+    assert abs(e - math.fsum(coeffs * ref)) < 1e-10
+
+
+def test_edge_cases(gpu_lib):
+    from paper_2303_03681_amd import binding
+    # one qubit
+    m = binding.Mps(1, 4, 1e-14, bits=[1])
+    plan = binding.PauliSum(np.array([[3], [0], [1]], np.uint8), np.array([2.0, 0.5, 1.0]))
+    e, per = m.expect(plan, "c128", per_term=True)
+    assert np.allclose(per, [-1.0, 1.0, 0.0], atol=1e-14) and abs(e - (-1.5)) < 1e-14
+    m.apply_gate(0, -1, np.array([[0, 1], [1, 0]]))
+    assert abs(m.expect(plan, "c128") - 2.5) < 1e-14
+    # empty sum and identity-only sum
+    m2 = binding.Mps(6, 4, 1e-14)
+    assert m2.expect(binding.PauliSum(np.zeros((0, 6), np.uint8), np.zeros(0))) == 0.0
+    assert abs(m2.expect(binding.PauliSum(np.zeros((1, 6), np.uint8), np.array([3.25]))) - 3.25) < 1e-14
+    # D = 1 keeps a product state through entangling gates (largest singular value only)
+    m3 = binding.Mps(4, 1, 0.0, bits=[1, 0, 1, 0])
+    m3.apply_gate(1, 2, np.kron(np.array([[0.6, 0.8], [-0.8, 0.6]]), np.eye(2)))
+    assert list(m3.bond_dims()) == [1, 1, 1, 1, 1]
+
+
+def test_error_paths_leave_state_unchanged(gpu_lib):
+    from paper_2303_03681_amd import binding
+    n = 6
+    m = binding.Mps(n, 8, 1e-14, bits=hf_bits(n, 3))
+    ang = workload_rng(9, 1).uniform(-np.pi, np.pi, size=(2, n, 2))
+    _apply(m, fuse_gates(brickwork_gates(n, ang), n))
+    plan = binding.PauliSum(np.eye(n, dtype=np.uint8) * 3, np.ones(n))
+    e0 = m.expect(plan)
+    dims0 = m.bond_dims().copy()
+    with pytest.raises(binding.MpsError) as ex:
+        m.apply_gate(2, 4, gate_cnot())
+    assert ex.value.name == "MPS_ERR_ARG"
+    bad = gate_cnot().copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(binding.MpsError) as ex:
+        m.apply_gate(1, 2, bad)
+    assert ex.value.name == "MPS_ERR_NONFINITE"
+    with pytest.raises(binding.MpsError) as ex:
+        m.expect(binding.PauliSum(np.zeros((1, n + 1), np.uint8), np.ones(1)))
+    assert ex.value.name == "MPS_ERR_ARG"
+    assert list(m.bond_dims()) == list(dims0)
+    assert abs(m.expect(plan) - e0) < 1e-13
+    with pytest.raises(binding.MpsError) as ex:
+        binding.Mps(40, 256, 1e-14, hbm_budget_bytes=1 << 20)
+    assert ex.value.name == "MPS_ERR_BUDGET"
+    # the sweep limit turns into MPS_ERR_NOCONV and the gate is not applied
+    m4 = binding.Mps(8, 16, 1e-14, bits=hf_bits(8, 4), max_jacobi_sweeps=1)
+    ang = workload_rng(10, 1).uniform(-np.pi, np.pi, size=(3, 8, 2))
+    gates = fuse_gates(brickwork_gates(8, ang), 8)
+    q0, q1, u = pack_gates(gates)
+    with pytest.raises(binding.MpsError) as ex:
+        m4.apply_gates(q0, q1, u)
+    assert ex.value.name == "MPS_ERR_NOCONV"
+
+
+def test_canonicalize_idempotent(gpu_lib):
+    from paper_2303_03681_amd import binding
+    n = 10
+    ang = workload_rng(12, 1).uniform(-np.pi, np.pi, size=(5, n, 2))
+    m = binding.Mps(n, 6, 1e-14, bits=hf_bits(n, 5))
+    _apply(m, fuse_gates(brickwork_gates(n, ang), n))
+    m.canonicalize()
+    lam1 = [m.export_site(q)[1] for q in range(n)]
+    m.canonicalize()
+    assert abs(m.norm() - 1) < 1e-13
+    for q in range(n):
+        assert np.max(np.abs(m.export_site(q)[1] - lam1[q])) < 1e-12
+    for q in range(n):
+        B, _ = m.export_site(q)
+        g = np.einsum("sab,scb->ac", B, B.conj())
+        assert np.max(np.abs(g - np.eye(g.shape[0]))) < 1e-12
