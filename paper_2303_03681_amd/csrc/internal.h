@@ -34,9 +34,10 @@ struct MixItem {          // Q mixing (Eq. C) and lambda row scaling (Eq. C~)
 struct JacItem {          // one-sided Jacobi on the n row vectors (length m) of w
   double2* w;
   const double* fro2;     // ||w||_F^2 (invariant under the rotations)
-  int* rot;               // rotation count per sweep [max_sweeps]
+  int* rot;               // rotation count of sweep s at rot[s * rot_stride]
   int* sweeps_done;       // single-launch mode: sweeps executed (negative: no convergence)
   int n, m, wblk, nb;     // vectors, length, vectors per block, number of blocks (even)
+  int rot_stride;
 };
 
 enum FinalizeMode { FIN_GATE = 0, FIN_LEFT = 1, FIN_RIGHT = 2 };
@@ -113,6 +114,8 @@ hipError_t launch_mix(const MixItem* items_dev, int items, int max_dldr, hipStre
 hipError_t configure_jacobi_lds(size_t bytes);
 hipError_t launch_jacobi_block(const JacItem* items_dev, int items, int max_pairs, int round,
                                int sweep, double eps_scale, size_t lds_bytes, hipStream_t s);
+hipError_t launch_jacobi_reg(const JacItem* items_dev, int items, int max_pairs, int round,
+                             int sweep, double eps_scale, int max_m, hipStream_t s);
 hipError_t launch_jacobi_single(const JacItem* items_dev, int items, int max_sweeps,
                                 double eps_scale, size_t lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const FinItem* items_dev, int items, hipStream_t s);

@@ -24,9 +24,23 @@ namespace mps {
 
 namespace {
 
+// Sum over the 64 lanes of a wave, the same bits in every lane (each step
+// adds a and b in both orders, and a + b == b + a exactly): DPP moves within
+// rows of 16 lanes, then two cross-row exchanges.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -228,7 +242,8 @@ __device__ int jacobi_local_sweep(double2* sm, const int* gidx, int nloc, int m,
 }
 
 // Block mode: one workgroup per block pair of round `round`; the pair's
-// 2*wblk vectors are staged in LDS, swept once, and written back.
+// 2*wblk vectors are staged in LDS, swept once, and written back.  Each block
+// is a contiguous run of vectors, so staging is two flat, coalesced copies.
 __global__ __launch_bounds__(512) void jacobi_block_kernel(const JacItem* items, int max_pairs,
                                                            int round, int sweep, double eps_scale) {
   extern __shared__ double2 sm[];
@@ -239,7 +254,7 @@ __global__ __launch_bounds__(512) void jacobi_block_kernel(const JacItem* items,
   const JacItem it = items[item];
   const int nb = it.nb;
   if (p >= nb / 2 || round >= nb - 1) return;
-  if (sweep > 0 && it.rot[sweep - 1] == 0) return;  // converged in the previous sweep
+  if (sweep > 0 && it.rot[(sweep - 1) * it.rot_stride] == 0) return;  // converged
   const int w = it.wblk, m = it.m, n = it.n;
   const int bp = (p == 0) ? 0 : 1 + ((p - 1 + round) % (nb - 1));
   const int bq = 1 + ((nb - 2 - p + round) % (nb - 1));
@@ -248,26 +263,257 @@ __global__ __launch_bounds__(512) void jacobi_block_kernel(const JacItem* items,
     const int g = lv < w ? bp * w + lv : bq * w + (lv - w);
     gidx[lv] = g < n ? g : -1;
   }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nloc * m; idx += blockDim.x) {
-    const int lv = idx / m;
-    const int e = idx - lv * m;
-    const int g = gidx[lv];
-    sm[idx] = g >= 0 ? it.w[(size_t)g * m + e] : make_double2(0.0, 0.0);
-  }
+  const int vp = max(0, min(w, n - bp * w)), vq = max(0, min(w, n - bq * w));
+  const size_t cp = (size_t)vp * m, cq = (size_t)vq * m, wm = (size_t)w * m;
+  const double2* srcp = it.w + (size_t)bp * w * m;
+  const double2* srcq = it.w + (size_t)bq * w * m;
+#pragma unroll 4
+  for (size_t i = threadIdx.x; i < wm; i += 512) sm[i] = i < cp ? srcp[i] : make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (size_t i = threadIdx.x; i < wm; i += 512) sm[wm + i] = i < cq ? srcq[i] : make_double2(0.0, 0.0);
   __syncthreads();
   const double eps = eps_scale * (double)m;
   const double floor = eps * eps * (*it.fro2);
   const int rot = jacobi_local_sweep(sm, gidx, nloc, m, eps, floor, &s_rot);
   if (rot > 0) {
-    for (int idx = threadIdx.x; idx < nloc * m; idx += blockDim.x) {
-      const int lv = idx / m;
-      const int e = idx - lv * m;
-      const int g = gidx[lv];
-      if (g >= 0) it.w[(size_t)g * m + e] = sm[idx];
-    }
-    if (threadIdx.x == 0) atomicAdd(&it.rot[sweep], rot);
+    double2* dstp = it.w + (size_t)bp * w * m;
+    double2* dstq = it.w + (size_t)bq * w * m;
+#pragma unroll 4
+    for (size_t i = threadIdx.x; i < cp; i += 512) dstp[i] = sm[i];
+#pragma unroll 4
+    for (size_t i = threadIdx.x; i < cq; i += 512) dstq[i] = sm[wm + i];
+    if (threadIdx.x == 0) atomicAdd(&it.rot[sweep * it.rot_stride], rot);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident block Jacobi.  A workgroup of JW = 8 waves owns one block
+// pair (2 x 8 vectors); each lane keeps E elements (e = lane + 64 k) of the
+// vectors its wave holds, so dot products and rotations never touch LDS.
+// Outer round 0 of a sweep pairs every block with exactly one other block and
+// sweeps all 120 pairs of the 16 vectors (circle method, both vectors of a
+// wave move each inner round); every later outer round only needs the 64
+// cross pairs: each wave keeps its resident vector from block p and the
+// travellers from block q move one wave along per inner round.  Over one
+// outer sweep every pair of the matrix is visited once.
+constexpr int JW = 8;
+
+template <int E>
+struct RegVec {
+  double2 v[E];
+};
+
+template <int E>
+__device__ __forceinline__ void rv_load(RegVec<E>& r, const double2* src, int valid, int m, int lane) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = lane + 64 * k;
+    r.v[k] = (valid && e < m) ? src[e] : make_double2(0.0, 0.0);
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void rv_store(const RegVec<E>& r, double2* dst, int m, int lane) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = lane + 64 * k;
+    if (e < m) dst[e] = r.v[k];
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void rv_to_lds(const RegVec<E>& r, double2* slot, int lane) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) slot[64 * k + lane] = r.v[k];
+}
+
+template <int E>
+__device__ __forceinline__ void rv_from_lds(RegVec<E>& r, const double2* slot, int lane) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) r.v[k] = slot[64 * k + lane];
+}
+
+// Algorithm 1's pair step on register vectors a (lower global index) and b.
+template <int E>
+__device__ __forceinline__ bool jacobi_pair_reg(RegVec<E>& a, RegVec<E>& b, double eps, double floor) {
+  double bii = 0.0, bjj = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 x = a.v[k], y = b.v[k];
+    bii += x.x * x.x + x.y * x.y;
+    bjj += y.x * y.x + y.y * y.y;
+    br += x.x * y.x + x.y * y.y;
+    bi += x.x * y.y - x.y * y.x;
+  }
+  bii = wave_sum(bii);
+  bjj = wave_sum(bjj);
+  br = wave_sum(br);
+  bi = wave_sum(bi);
+  const double mag = sqrt(br * br + bi * bi);
+  if (!(mag > floor) || !(mag > eps * sqrt(bii * bjj))) return false;
+  const double tau = (bii - bjj) / (2.0 * mag);
+  const double at = fabs(tau);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  const double t = at > 1e100 ? sg * (0.5 / at) : sg / (at + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = t * c;
+  const double er = br / mag, ei = bi / mag;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 x = a.v[k], y = b.v[k];
+    const double cbr = er * y.x + ei * y.y, cbi = er * y.y - ei * y.x;  // conj(e) b
+    const double ear = er * x.x - ei * x.y, eai = er * x.y + ei * x.x;  // e a
+    a.v[k] = make_double2(c * x.x + s * cbr, c * x.y + s * cbi);
+    b.v[k] = make_double2(c * y.x - s * ear, c * y.y - s * eai);
+  }
+  return true;
+}
+
+template <int E>
+__device__ __forceinline__ bool jacobi_pair_ordered(RegVec<E>& x, int gx, RegVec<E>& y, int gy,
+                                                    double eps, double floor) {
+  if (gx < 0 || gy < 0) return false;
+  return gx < gy ? jacobi_pair_reg<E>(x, y, eps, floor) : jacobi_pair_reg<E>(y, x, eps, floor);
+}
+
+// Common prologue of the register kernels: which block pair this workgroup
+// owns, or false if it has nothing to do (padding pair, converged item).
+struct RegCtx {
+  JacItem it;
+  int bp, bq;
+  double eps, floor;
+};
+
+__device__ __forceinline__ bool reg_prologue(const JacItem* items, int max_pairs, int round,
+                                             int sweep, double eps_scale, RegCtx& c) {
+  const int item = blockIdx.x / max_pairs;
+  const int p = blockIdx.x - item * max_pairs;
+  c.it = items[item];
+  const int nb = c.it.nb;
+  if (p >= nb / 2 || round >= nb - 1) return false;
+  if (sweep > 0 && c.it.rot[(sweep - 1) * c.it.rot_stride] == 0) return false;  // converged
+  c.bp = (p == 0) ? 0 : 1 + ((p - 1 + round) % (nb - 1));
+  c.bq = 1 + ((nb - 2 - p + round) % (nb - 1));
+  c.eps = eps_scale * (double)c.it.m;
+  c.floor = c.eps * c.eps * (*c.it.fro2);
+  return true;
+}
+
+template <int E>
+__device__ __forceinline__ void reg_epilogue(const RegCtx& c, int rot, int* s_rot, const RegVec<E>& x,
+                                             int gx, const RegVec<E>& y, int gy, int sweep) {
+  const int lane = threadIdx.x & 63;
+  if (lane == 0 && rot) atomicAdd(s_rot, rot);
+  __syncthreads();
+  if (*s_rot > 0) {
+    if (gx >= 0) rv_store<E>(x, c.it.w + (size_t)gx * c.it.m, c.it.m, lane);
+    if (gy >= 0) rv_store<E>(y, c.it.w + (size_t)gy * c.it.m, c.it.m, lane);
+    if (threadIdx.x == 0) atomicAdd(&c.it.rot[sweep * c.it.rot_stride], *s_rot);
+  }
+}
+
+// Outer round 0: all pairs of the 16 vectors of blocks bp and bq by the
+// circle method.  Wave i holds positions i (x) and 15 - i (y); positions
+// 1..15 advance by one each inner round through 2 x 8 LDS slots.
+template <int E>
+__global__ __launch_bounds__(JW * 64) void jacobi_reg_full_kernel(const JacItem* items, int max_pairs,
+                                                                  int round, int sweep,
+                                                                  double eps_scale) {
+  extern __shared__ double2 slots[];  // 2 * JW slots of 64 * E elements
+  __shared__ int s_rot;
+  __shared__ int g_top[JW], g_bot[JW];
+  RegCtx c;
+  if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
+  const int m = c.it.m, n = c.it.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_rot = 0;
+  RegVec<E> x, y;
+  int gx = c.bp * JW + wv, gy = c.bq * JW + (JW - 1 - wv);
+  gx = gx < n ? gx : -1;
+  gy = gy < n ? gy : -1;
+  rv_load<E>(x, c.it.w + (size_t)max(gx, 0) * m, gx >= 0, m, lane);
+  rv_load<E>(y, c.it.w + (size_t)max(gy, 0) * m, gy >= 0, m, lane);
+  double2* top = slots;
+  double2* bot = slots + (size_t)JW * 64 * E;
+  int rot = 0;
+  for (int t = 0; t < 2 * JW - 1; ++t) {
+    rot += jacobi_pair_ordered<E>(x, gx, y, gy, c.eps, c.floor);
+    rv_to_lds<E>(x, top + (size_t)wv * 64 * E, lane);
+    rv_to_lds<E>(y, bot + (size_t)wv * 64 * E, lane);
+    if (lane == 0) {
+      g_top[wv] = gx;
+      g_bot[wv] = gy;
+    }
+    __syncthreads();
+    // new pos j+1 <- old pos j for j = 1..14, new pos 1 <- old pos 15, pos 0 fixed
+    if (wv >= 2) { rv_from_lds<E>(x, top + (size_t)(wv - 1) * 64 * E, lane); gx = g_top[wv - 1]; }
+    if (wv == 1) { rv_from_lds<E>(x, bot, lane); gx = g_bot[0]; }
+    if (wv <= JW - 2) { rv_from_lds<E>(y, bot + (size_t)(wv + 1) * 64 * E, lane); gy = g_bot[wv + 1]; }
+    if (wv == JW - 1) { rv_from_lds<E>(y, top + (size_t)(JW - 1) * 64 * E, lane); gy = g_top[JW - 1]; }
+    __syncthreads();
+  }
+  reg_epilogue<E>(c, rot, &s_rot, x, gx, y, gy, sweep);
+}
+
+// Outer rounds >= 1: the 64 cross pairs of blocks bp and bq.  Wave i keeps
+// resident vector bp*8 + i; the travellers from block bq move one wave along
+// per inner round through 8 LDS slots.
+template <int E>
+__global__ __launch_bounds__(JW * 64) void jacobi_reg_cross_kernel(const JacItem* items, int max_pairs,
+                                                                   int round, int sweep,
+                                                                   double eps_scale) {
+  extern __shared__ double2 slots[];  // JW slots of 64 * E elements
+  __shared__ int s_rot;
+  RegCtx c;
+  if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
+  const int m = c.it.m, n = c.it.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_rot = 0;
+  RegVec<E> x, y;
+  int gx = c.bp * JW + wv;
+  gx = gx < n ? gx : -1;
+  int src = wv;  // home wave of the traveller currently held
+  int gy = c.bq * JW + src;
+  gy = gy < n ? gy : -1;
+  rv_load<E>(x, c.it.w + (size_t)max(gx, 0) * m, gx >= 0, m, lane);
+  rv_load<E>(y, c.it.w + (size_t)max(gy, 0) * m, gy >= 0, m, lane);
+  int rot = 0;
+  for (int t = 0; t < JW; ++t) {
+    rot += jacobi_pair_ordered<E>(x, gx, y, gy, c.eps, c.floor);
+    if (t == JW - 1) break;
+    rv_to_lds<E>(y, slots + (size_t)wv * 64 * E, lane);
+    __syncthreads();
+    rv_from_lds<E>(y, slots + (size_t)((wv + JW - 1) % JW) * 64 * E, lane);
+    src = (src + JW - 1) % JW;
+    gy = c.bq * JW + src;
+    gy = gy < n ? gy : -1;
+    __syncthreads();
+  }
+  __syncthreads();
+  reg_epilogue<E>(c, rot, &s_rot, x, gx, y, gy, sweep);
+}
+
+template <int E>
+hipError_t launch_reg_e(const JacItem* items_dev, int items, int max_pairs, int round, int sweep,
+                        double eps_scale, hipStream_t s) {
+  const dim3 grid(items * max_pairs), block(JW * 64);
+  if (round == 0)
+    hipLaunchKernelGGL(jacobi_reg_full_kernel<E>, grid, block, 2 * JW * 64 * E * sizeof(double2), s,
+                       items_dev, max_pairs, round, sweep, eps_scale);
+  else
+    hipLaunchKernelGGL(jacobi_reg_cross_kernel<E>, grid, block, JW * 64 * E * sizeof(double2), s,
+                       items_dev, max_pairs, round, sweep, eps_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_reg(const JacItem* items_dev, int items, int max_pairs, int round,
+                             int sweep, double eps_scale, int max_m, hipStream_t s) {
+  if (items <= 0 || max_pairs <= 0) return hipSuccess;
+  if (max_m <= 64) return launch_reg_e<1>(items_dev, items, max_pairs, round, sweep, eps_scale, s);
+  if (max_m <= 128) return launch_reg_e<2>(items_dev, items, max_pairs, round, sweep, eps_scale, s);
+  if (max_m <= 256) return launch_reg_e<4>(items_dev, items, max_pairs, round, sweep, eps_scale, s);
+  if (max_m <= 512) return launch_reg_e<8>(items_dev, items, max_pairs, round, sweep, eps_scale, s);
+  return hipErrorInvalidValue;
 }
 
 // Single mode: the whole matrix fits in LDS; sweep until a sweep performs no
@@ -302,11 +548,16 @@ __global__ __launch_bounds__(512) void jacobi_single_kernel(const JacItem* items
 }
 
 hipError_t configure_jacobi_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)jacobi_single_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[] = {(const void*)jacobi_block_kernel, (const void*)jacobi_single_kernel,
+                       (const void*)jacobi_reg_full_kernel<1>, (const void*)jacobi_reg_full_kernel<2>,
+                       (const void*)jacobi_reg_full_kernel<4>, (const void*)jacobi_reg_full_kernel<8>,
+                       (const void*)jacobi_reg_cross_kernel<1>, (const void*)jacobi_reg_cross_kernel<2>,
+                       (const void*)jacobi_reg_cross_kernel<4>, (const void*)jacobi_reg_cross_kernel<8>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_jacobi_block(const JacItem* items_dev, int items, int max_pairs, int round,

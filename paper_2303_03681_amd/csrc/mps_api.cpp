@@ -228,7 +228,7 @@ mps_status ensure_lds(mps_state* h) {
   size_t b = (size_t)v;
   if (b > 160 * 1024) b = 160 * 1024;
   b = b > 8 * 1024 ? b - 8 * 1024 : b;  // room for the kernels' static shared arrays
-  if (b > 128 * 1024) b = 128 * 1024;
+  if (b > 152 * 1024) b = 152 * 1024;
   HIP_TRY(h, configure_jacobi_lds(b));
   g_lds_budget = b;
   return MPS_OK;
@@ -299,23 +299,36 @@ mps_status ensure_ws(mps_state* h, int items) {
 // batched one-sided Jacobi over items already described in host vectors
 
 struct JacobiPlanHost {
-  std::vector<JacItem> single, block;
+  std::vector<JacItem> single, reg, block;  // LDS single-launch, register blocks, LDS blocks
   size_t single_lds = 0, block_lds = 0;
+  int reg_pairs = 0, reg_rounds = 0, reg_max_m = 0;
   int block_pairs = 0, block_rounds = 0;
 };
+
+constexpr int kRegBlock = 8;     // vectors per block of the register kernels (one per wave)
+constexpr int kRegMaxLen = 512;  // longest vector the register kernels hold
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
   for (JacItem it : all) {
     const size_t per_vec = (size_t)it.m * sizeof(double2);
-    const int max_vec = (int)std::max<size_t>(2, budget / per_vec);
     const int nloc = (it.n + 1) & ~1;
-    if (nloc <= max_vec && nloc <= 1024) {
+    if (nloc <= 2 * kRegBlock && (size_t)it.n * per_vec <= budget) {
       it.wblk = nloc;
       it.nb = 1;
       jp.single.push_back(it);
       jp.single_lds = std::max(jp.single_lds, (size_t)it.n * per_vec);
+    } else if (it.m <= kRegMaxLen) {
+      int nb = (it.n + kRegBlock - 1) / kRegBlock;
+      if (nb & 1) ++nb;
+      it.wblk = kRegBlock;
+      it.nb = nb;
+      jp.reg.push_back(it);
+      jp.reg_pairs = std::max(jp.reg_pairs, nb / 2);
+      jp.reg_rounds = std::max(jp.reg_rounds, nb - 1);
+      jp.reg_max_m = std::max(jp.reg_max_m, it.m);
     } else {
+      const int max_vec = (int)std::max<size_t>(2, budget / per_vec);
       int w = std::min(128, max_vec / 2);
       if (w < 1) w = 1;
       int nb = (it.n + w - 1) / w;
@@ -331,74 +344,86 @@ void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
 }
 
 // Runs Algorithm 1 on every item (vectors in it.w, ||w||_F^2 in it.fro2 already
-// on device).  Requires item.rot zeroed for max_sweeps entries.  On return
-// (after a stream sync) `sweeps_out[i]` holds the sweeps used, or -1.
+// on device).  Item i must use rot = all[0].rot + i with rot_stride =
+// all.size(), zeroed for max_sweeps sweeps.  On return (after a stream sync)
+// `sweeps_out[i]` holds the sweeps used, or -1 if the sweep limit was hit.
 mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc_off,
                       std::vector<int>& sweeps_out) {
+  const int count = (int)all.size();
+  for (int i = 0; i < count; ++i)
+    if (all[i].rot != all[0].rot + i || all[i].rot_stride != count)
+      return fail(MPS_ERR_STATE, "internal: Jacobi rotation counters not laid out [sweep][item]");
   JacobiPlanHost jp;
   plan_jacobi(all, jp);
-  const size_t bytes = (jp.single.size() + jp.block.size()) * sizeof(JacItem);
+  const size_t bytes = (jp.single.size() + jp.reg.size() + jp.block.size()) * sizeof(JacItem);
   mps_status st = ensure_desc(h, desc_off + bytes);
   if (st != MPS_OK) return st;
   char* base = (char*)h->d_desc + desc_off;
   JacItem* d_single = (JacItem*)base;
-  JacItem* d_block = d_single + jp.single.size();
-  std::vector<JacItem> both(jp.single);
-  both.insert(both.end(), jp.block.begin(), jp.block.end());
-  if ((st = upload(h, base, both.data(), bytes)) != MPS_OK) return st;
+  JacItem* d_reg = d_single + jp.single.size();
+  JacItem* d_block = d_reg + jp.reg.size();
+  std::vector<JacItem> packed(jp.single);
+  packed.insert(packed.end(), jp.reg.begin(), jp.reg.end());
+  packed.insert(packed.end(), jp.block.begin(), jp.block.end());
+  if ((st = upload(h, base, packed.data(), bytes)) != MPS_OK) return st;
   if (!jp.single.empty())
     HIP_TRY(h, launch_jacobi_single(d_single, (int)jp.single.size(), h->max_sweeps, kEpsScale,
                                     jp.single_lds, h->stream));
-  std::vector<int> block_sweeps(jp.block.size(), -1);
-  if (!jp.block.empty()) {
-    std::vector<int> rot(jp.block.size());
+  // per item (caller order): first rotation-free sweep, from the counters
+  std::vector<int> first_zero(count, -1);
+  std::vector<char> is_multi(count, 0);
+  for (const JacItem& b : jp.reg) is_multi[b.rot - all[0].rot] = 1;
+  for (const JacItem& b : jp.block) is_multi[b.rot - all[0].rot] = 1;
+  const int nmulti = (int)(jp.reg.size() + jp.block.size());
+  if (nmulti > 0) {
+    std::vector<int> rot(count);
     int done = 0;
-    for (int sw = 0; sw < h->max_sweeps && done < (int)jp.block.size(); ++sw) {
-      for (int r = 0; r < jp.block_rounds; ++r)
-        HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
-                                       kEpsScale, jp.block_lds, h->stream));
-      if (sw >= 3 || sw == h->max_sweeps - 1) {
-        for (size_t i = 0; i < jp.block.size(); ++i)
-          HIP_TRY(h, hipMemcpyAsync(&rot[i], jp.block[i].rot + sw, sizeof(int),
-                                    hipMemcpyDeviceToHost, h->stream));
-        if ((st = sync(h)) != MPS_OK) return st;
-        done = 0;
-        for (size_t i = 0; i < jp.block.size(); ++i) {
-          if (block_sweeps[i] < 0 && rot[i] == 0) block_sweeps[i] = sw + 1;
-          if (block_sweeps[i] >= 0) ++done;
-        }
+    const int rounds = std::max(jp.reg_rounds, jp.block_rounds);
+    for (int sw = 0; sw < h->max_sweeps && done < nmulti; ++sw) {
+      for (int r = 0; r < rounds; ++r) {
+        if (!jp.reg.empty() && r < jp.reg_rounds)
+          HIP_TRY(h, launch_jacobi_reg(d_reg, (int)jp.reg.size(), jp.reg_pairs, r, sw, kEpsScale,
+                                       jp.reg_max_m, h->stream));
+        if (!jp.block.empty() && r < jp.block_rounds)
+          HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
+                                         kEpsScale, jp.block_lds, h->stream));
       }
-    }
-    // a sweep before the first check may already have been rotation-free
-    for (size_t i = 0; i < jp.block.size(); ++i) {
-      if (block_sweeps[i] >= 0) {
-        std::vector<int> r(block_sweeps[i]);
-        HIP_TRY(h, hipMemcpyAsync(r.data(), jp.block[i].rot, sizeof(int) * r.size(),
+      if (sw >= 3 || sw == h->max_sweeps - 1) {
+        HIP_TRY(h, hipMemcpyAsync(rot.data(), all[0].rot + (size_t)sw * count, sizeof(int) * count,
                                   hipMemcpyDeviceToHost, h->stream));
         if ((st = sync(h)) != MPS_OK) return st;
-        for (int s = 0; s < (int)r.size(); ++s)
-          if (r[s] == 0) {
-            block_sweeps[i] = s + 1;
-            break;
-          }
+        done = 0;
+        for (int i = 0; i < count; ++i)
+          if (is_multi[i] && rot[i] == 0) ++done;
       }
     }
+    // exact first rotation-free sweep of every multi-launch item
+    std::vector<int> hist((size_t)h->max_sweeps * count);
+    HIP_TRY(h, hipMemcpyAsync(hist.data(), all[0].rot, sizeof(int) * hist.size(),
+                              hipMemcpyDeviceToHost, h->stream));
+    if ((st = sync(h)) != MPS_OK) return st;
+    for (int i = 0; i < count; ++i)
+      if (is_multi[i])
+        for (int sw = 0; sw < h->max_sweeps; ++sw)
+          if (hist[(size_t)sw * count + i] == 0) {
+            first_zero[i] = sw + 1;
+            break;
+          }
   }
   std::vector<int> single_sweeps(jp.single.size());
-  for (size_t i = 0; i < jp.single.size(); ++i)
-    HIP_TRY(h, hipMemcpyAsync(&single_sweeps[i], jp.single[i].sweeps_done, sizeof(int),
+  for (size_t j = 0; j < jp.single.size(); ++j)
+    HIP_TRY(h, hipMemcpyAsync(&single_sweeps[j], jp.single[j].sweeps_done, sizeof(int),
                               hipMemcpyDeviceToHost, h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
-  // map back to the caller's order (items are identified by their w pointer)
-  sweeps_out.assign(all.size(), -1);
-  for (size_t i = 0; i < all.size(); ++i) {
-    for (size_t j = 0; j < jp.single.size(); ++j)
-      if (jp.single[j].w == all[i].w) sweeps_out[i] = single_sweeps[j] > 0 ? single_sweeps[j] : -1;
-    for (size_t j = 0; j < jp.block.size(); ++j)
-      if (jp.block[j].w == all[i].w) sweeps_out[i] = block_sweeps[j];
+  sweeps_out.assign(count, -1);
+  for (int i = 0; i < count; ++i)
+    if (is_multi[i]) sweeps_out[i] = first_zero[i];
+  for (size_t j = 0; j < jp.single.size(); ++j) {
+    const int i = (int)(jp.single[j].rot - all[0].rot);
+    sweeps_out[i] = single_sweeps[j] > 0 ? single_sweeps[j] : -1;
   }
-  for (int s : sweeps_out)
-    if (s > 0) h->tm.jacobi_sweeps += s;
+  for (int v : sweeps_out)
+    if (v > 0) h->tm.jacobi_sweeps += v;
   return MPS_OK;
 }
 
@@ -423,8 +448,7 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
     double2* w = h->ws_w + (size_t)b * h->ws_stride;
     th[b] = ThetaItem{h->cur(q), h->cur(q + 1), c, dl, dm, dr};
     mx[b] = MixItem{c, w, h->lcur(q), h->d_gates + (size_t)gidx[b] * 16, h->d_fro2 + b, dl, dr};
-    jc[b] = JacItem{w, h->d_fro2 + b, h->d_rot + (size_t)b * h->max_sweeps, h->d_sweeps + b,
-                    2 * dl, 2 * dr, 0, 0};
+    jc[b] = JacItem{w, h->d_fro2 + b, h->d_rot + b, h->d_sweeps + b, 2 * dl, 2 * dr, 0, 0, items};
     const int capk = h->cap[q + 1];
     fn[b] = FinItem{w, h->spare(q + 1), h->lspare(q + 1), h->d_k + b, h->d_scale + b,
                     h->d_disc + b, h->d_status + b, 2 * dl, 2 * dr, capk, h->cutoff, FIN_GATE};
@@ -531,7 +555,7 @@ mps_status canonicalize_impl(mps_state* h) {
     HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double), h->stream));
     HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * h->max_sweeps, h->stream));
     HIP_TRY(h, launch_fro2(W, db * m, h->d_fro2, h->stream));
-    std::vector<JacItem> jc{JacItem{W, h->d_fro2, h->d_rot, h->d_sweeps, db, m, 0, 0}};
+    std::vector<JacItem> jc{JacItem{W, h->d_fro2, h->d_rot, h->d_sweeps, db, m, 0, 0, 1}};
     if ((st = run_jacobi(h, jc, 1024, sweeps)) != MPS_OK) return st;
     if (sweeps[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi did not converge in canonicalisation");
     HIP_TRY(h, launch_finalize((const FinItem*)(d + 512), 1, h->stream));
@@ -567,7 +591,7 @@ mps_status canonicalize_impl(mps_state* h) {
     HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double), h->stream));
     HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * h->max_sweeps, h->stream));
     HIP_TRY(h, launch_fro2(W, dl * m, h->d_fro2, h->stream));
-    std::vector<JacItem> jc{JacItem{W, h->d_fro2, h->d_rot, h->d_sweeps, dl, m, 0, 0}};
+    std::vector<JacItem> jc{JacItem{W, h->d_fro2, h->d_rot, h->d_sweeps, dl, m, 0, 0, 1}};
     if ((st = run_jacobi(h, jc, 1024, sweeps)) != MPS_OK) return st;
     if (sweeps[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi did not converge in canonicalisation");
     HIP_TRY(h, launch_finalize((const FinItem*)(d + 512), 1, h->stream));
@@ -1301,7 +1325,7 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
   HIP_TRY(h, hipMemset(rot, 0, sizeof(int) * h->max_sweeps));
   HIP_TRY(h, launch_fro2(w, n_vec * m, fro2, h->stream));
   std::vector<int> swp;
-  std::vector<JacItem> jc{JacItem{w, fro2, rot, sw, n_vec, m, 0, 0}};
+  std::vector<JacItem> jc{JacItem{w, fro2, rot, sw, n_vec, m, 0, 0, 1}};
   if ((st = run_jacobi(h, jc, 0, swp)) != MPS_OK) return st;
   if (swp[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi SVD did not converge");
   FinItem fi{w, out, lam, k, scale, disc, status, n_vec, m, n_vec, 0.0, FIN_GATE};
