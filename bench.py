@@ -219,6 +219,9 @@ def main():
         "phases_ms_per_step": {"gates": tm["gates_ms"] / K, "canonicalize": tm["canon_ms"] / K,
                                "expect": tm["expect_ms"] / K, "env_kernels": tm["env_ms"] / K,
                                "close_kernels": tm["close_ms"] / K},
+        "close": {"tflops_fp64": (tm["close_flops"] / (tm["close_ms"] * 1e-3) / 1e12
+                                  if tm["close_ms"] > 0 else 0.0),
+                  "gflop_per_step": tm["close_flops"] / K / 1e9},
         "jacobi_sweeps_per_step": tm["jacobi_sweeps"] / K,
         "plan": st,
         "bond_dims_max": int(dims.max()),

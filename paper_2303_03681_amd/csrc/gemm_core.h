@@ -9,13 +9,17 @@
 // letter's block swap and phase are folded into the operand fetch instead of
 // being materialised.
 //
-// Problem interface: typedef T (compute type) and Ctx (per-item state),
-// constexpr A_CONTIG_K / B_CONTIG_N (which index is contiguous in memory, to
-// pick a coalesced load order) and REAL_ONLY, plus
+// Problem interface: typedef T (compute type), Ctx (per-item state), RowA
+// and ColB (per-row / per-column handles, e.g. a row pointer), constexpr
+// A_CONTIG_K / B_CONTIG_N (which index is contiguous in memory, to pick a
+// coalesced load order) and REAL_ONLY, plus
 //   Ctx context(int item) const;   static void dims(const Ctx&, int& M, int& N, int& K);
-//   static C2 loadA(const Ctx&, int i, int k);  static C2 loadB(const Ctx&, int k, int j);
+//   static RowA rowA(const Ctx&, int i);   static ColB colB(const Ctx&, int j);
+//   static C2 loadA(const Ctx&, RowA, int i, int k);  static C2 loadB(const Ctx&, ColB, int k, int j);
 //   static void store(const Ctx&, int i, int j, T re, T im);
-// The core only calls loadA/loadB/store with in-range indices.
+// Each thread's rows of A and columns of B are fixed for the whole K loop,
+// so their handles are computed once.  The core only calls the loads and
+// stores with in-range indices.
 //
 // Tile: BM x BN per workgroup of 256 threads (4 wave64s in a 2x2 grid, each
 // wave owning (BM/2) x (BN/2) as 16x16 MFMA blocks), K staged through LDS in
@@ -99,6 +103,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(P p, int tiles_m, int tiles_
   const int lk = lane >> 4;
 
   C2 ra[A_EL], rb[B_EL];
+  typename P::RowA ha[A_EL];
+  typename P::ColB hb[B_EL];
 
   auto a_coord = [&](int e, int& ii, int& kk) {
     const int idx = tid + e * NT;
@@ -110,6 +116,20 @@ __global__ __launch_bounds__(256) void cgemm_kernel(P p, int tiles_m, int tiles_
     if (P::B_CONTIG_N) { jj = idx % BN; kk = idx / BN; }
     else { kk = idx % BK; jj = idx / BK; }
   };
+#pragma unroll
+  for (int e = 0; e < A_EL; ++e) {
+    int ii, kk;
+    a_coord(e, ii, kk);
+    const int gi = m0 + ii;
+    if (gi < M) ha[e] = P::rowA(ctx, gi);
+  }
+#pragma unroll
+  for (int e = 0; e < B_EL; ++e) {
+    int kk, jj;
+    b_coord(e, kk, jj);
+    const int gj = n0 + jj;
+    if (gj < N) hb[e] = P::colB(ctx, gj);
+  }
   auto load_tiles = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < A_EL; ++e) {
@@ -119,7 +139,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(P p, int tiles_m, int tiles_
       C2 v;
       v.x = T(0);
       v.y = T(0);
-      if (gi < M && gk < K) v = P::loadA(ctx, gi, gk);
+      if (gi < M && gk < K) v = P::loadA(ctx, ha[e], gi, gk);
       ra[e] = v;
     }
 #pragma unroll
@@ -130,7 +150,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(P p, int tiles_m, int tiles_
       C2 v;
       v.x = T(0);
       v.y = T(0);
-      if (gk < K && gj < N) v = P::loadB(ctx, gk, gj);
+      if (gk < K && gj < N) v = P::loadB(ctx, hb[e], gk, gj);
       rb[e] = v;
     }
   };

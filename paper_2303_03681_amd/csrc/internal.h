@@ -97,11 +97,14 @@ struct EnvChild {         // L' = sum_s A^{s+} (ph_s X^{s xor flip})
   int letter;             // 0 I, 1 X, 2 Y, 3 Z
 };
 
-struct GramItem {         // G[a][b] = Re sum_x L_a[x] R_b[x]  (closing traces)
+struct GramItem {         // G[a][b] = Re sum_x L_a[x] R_b[x]  (closing traces at one bond)
   const void* const* lptr;
   const void* const* rptr;
   double* g;              // (nl x nr)
   int nl, nr, kdim;
+};
+struct GramTile {         // one 64x64 block of some bond's G that a string needs
+  int item, r0, c0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -145,8 +148,8 @@ hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr,
                                int elem_bytes, hipStream_t s);
 hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,
                         hipStream_t s);
-hipError_t launch_gram(const GramItem* items_dev, int items, int max_nl, int max_nr, int elem_bytes,
-                       hipStream_t s);
+hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles,
+                       int elem_bytes, hipStream_t s);
 hipError_t launch_gather(const double* g, const int64_t* gidx, double* per_term, int64_t n,
                          hipStream_t s);
 hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n, double* out,

@@ -102,12 +102,15 @@ struct ThetaP {
     N = 2 * c.dr;
     K = c.dm;
   }
-  __device__ static double2 loadA(const Ctx& c, int i, int k) { return c.bl[(size_t)i * c.dm + k]; }
-  __device__ static double2 loadB(const Ctx& c, int k, int j) {
+  using RowA = const double2*;
+  using ColB = const double2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.bl + (size_t)i * c.dm; }
+  __device__ static ColB colB(const Ctx& c, int j) {
     const int s = j >= c.dr;
-    const int r = j - s * c.dr;
-    return c.br[((size_t)s * c.dm + k) * c.dr + r];
+    return c.br + (size_t)s * c.dm * c.dr + (j - s * c.dr);
   }
+  __device__ static double2 loadA(const Ctx&, RowA r, int, int k) { return r[k]; }
+  __device__ static double2 loadB(const Ctx& c, ColB b, int k, int) { return b[(size_t)k * c.dr]; }
   __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
     c.theta[(size_t)i * (2 * c.dr) + j] = make_double2(re, im);
   }
@@ -681,11 +684,14 @@ struct TruncP {
     N = c.k;
     K = 2 * c.dr;
   }
-  __device__ static double2 loadA(const Ctx& c, int i, int k) { return c.c[(size_t)i * (2 * c.dr) + k]; }
-  __device__ static double2 loadB(const Ctx& c, int k, int j) {
+  using RowA = const double2*;
+  using ColB = const double2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.c + (size_t)i * (2 * c.dr); }
+  __device__ static ColB colB(const Ctx& c, int j) { return c.v + (size_t)j * c.dr; }
+  __device__ static double2 loadA(const Ctx&, RowA r, int, int k) { return r[k]; }
+  __device__ static double2 loadB(const Ctx& c, ColB b, int k, int) {
     const int s = k >= c.dr;
-    const int r = k - s * c.dr;
-    const double2 v = c.v[((size_t)s * c.k + j) * c.dr + r];
+    const double2 v = b[(size_t)s * c.k * c.dr + (k - s * c.dr)];
     return make_double2(v.x, -v.y);
   }
   __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
@@ -713,10 +719,12 @@ struct CanonLeftP {  // W[beta][(s,alpha)] = sum_g B[s][g][beta] T[alpha][g]
     N = c.r;
     K = c.dg;
   }
-  __device__ static double2 loadA(const Ctx& c, int i, int k) {
-    return c.b[((size_t)c.s * c.dg + k) * c.db + i];
-  }
-  __device__ static double2 loadB(const Ctx& c, int k, int j) { return c.t[(size_t)j * c.dg + k]; }
+  using RowA = const double2*;
+  using ColB = const double2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.b + (size_t)c.s * c.dg * c.db + i; }
+  __device__ static ColB colB(const Ctx& c, int j) { return c.t + (size_t)j * c.dg; }
+  __device__ static double2 loadA(const Ctx& c, RowA r, int, int k) { return r[(size_t)k * c.db]; }
+  __device__ static double2 loadB(const Ctx&, ColB b, int k, int) { return b[k]; }
   __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
     c.w[(size_t)i * (2 * c.r) + c.s * c.r + j] = make_double2(re, im);
   }
@@ -733,11 +741,15 @@ struct CanonCarryLeftP {  // T'[a][beta] = sum_e conj(A[e][a]) W0[beta][e]
     N = c.db;
     K = c.m;
   }
-  __device__ static double2 loadA(const Ctx& c, int i, int k) {
-    const double2 v = c.a[(size_t)k * c.k + i];
+  using RowA = const double2*;
+  using ColB = const double2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.a + i; }
+  __device__ static ColB colB(const Ctx& c, int j) { return c.w0 + (size_t)j * c.m; }
+  __device__ static double2 loadA(const Ctx& c, RowA r, int, int k) {
+    const double2 v = r[(size_t)k * c.k];
     return make_double2(v.x, -v.y);
   }
-  __device__ static double2 loadB(const Ctx& c, int k, int j) { return c.w0[(size_t)j * c.m + k]; }
+  __device__ static double2 loadB(const Ctx&, ColB b, int k, int) { return b[k]; }
   __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
     c.t[(size_t)i * c.db + j] = make_double2(re, im);
   }
@@ -754,10 +766,12 @@ struct CanonRightP {  // W[alpha][(s,b')] = sum_beta A[s][alpha][beta] T[beta][b
     N = c.r;
     K = c.dm;
   }
-  __device__ static double2 loadA(const Ctx& c, int i, int k) {
-    return c.a[((size_t)c.s * c.dl + i) * c.dm + k];
-  }
-  __device__ static double2 loadB(const Ctx& c, int k, int j) { return c.t[(size_t)k * c.r + j]; }
+  using RowA = const double2*;
+  using ColB = const double2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.a + ((size_t)c.s * c.dl + i) * c.dm; }
+  __device__ static ColB colB(const Ctx& c, int j) { return c.t + j; }
+  __device__ static double2 loadA(const Ctx&, RowA r, int, int k) { return r[k]; }
+  __device__ static double2 loadB(const Ctx& c, ColB b, int k, int) { return b[(size_t)k * c.r]; }
   __device__ static void store(const Ctx& c, int i, int j, double re, double im) {
     c.w[(size_t)i * (2 * c.r) + c.s * c.r + j] = make_double2(re, im);
   }
@@ -850,12 +864,15 @@ struct EnvG1P {
     N = 2 * c.dr;
     K = c.dl;
   }
-  __device__ static C2 loadA(const Ctx& c, int i, int k) { return c.l[(size_t)i * c.dl + k]; }
-  __device__ static C2 loadB(const Ctx& c, int k, int j) {
+  using RowA = const C2*;
+  using ColB = const C2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.l + (size_t)i * c.dl; }
+  __device__ static ColB colB(const Ctx& c, int j) {
     const int s = j >= c.dr;
-    const int b = j - s * c.dr;
-    return c.site[((size_t)s * c.dl + k) * c.dr + b];
+    return c.site + (size_t)s * c.dl * c.dr + (j - s * c.dr);
   }
+  __device__ static C2 loadA(const Ctx&, RowA r, int, int k) { return r[k]; }
+  __device__ static C2 loadB(const Ctx& c, ColB b, int k, int) { return b[(size_t)k * c.dr]; }
   __device__ static void store(const Ctx& c, int i, int j, TT re, TT im) {
     C2 v;
     v.x = re;
@@ -889,18 +906,21 @@ struct EnvG2P {
     N = c.dr;
     K = 2 * c.dl;
   }
-  __device__ static C2 loadA(const Ctx& c, int i, int k) {
-    const int s = k >= c.dl;
-    const int a = k - s * c.dl;
-    C2 v = c.site[((size_t)s * c.dl + a) * c.dr + i];
+  using RowA = const C2*;
+  using ColB = const C2*;
+  __device__ static RowA rowA(const Ctx& c, int i) { return c.site + i; }
+  __device__ static ColB colB(const Ctx& c, int j) { return c.x + j; }
+  __device__ static C2 loadA(const Ctx& c, RowA r, int, int k) {
+    // element (beta, (s, alpha)) of [A^0+ | A^1+] is conj(A[s][alpha][beta]); k = s*dl + alpha
+    C2 v = r[(size_t)k * c.dr];
     v.y = -v.y;
     return v;
   }
-  __device__ static C2 loadB(const Ctx& c, int k, int j) {
+  __device__ static C2 loadB(const Ctx& c, ColB b, int k, int) {
     const int s = k >= c.dl;
     const int a = k - s * c.dl;
     const int flip = (c.letter == 1 || c.letter == 2) ? 1 : 0;
-    const C2 v = c.x[(size_t)a * (2 * c.dr) + (s ^ flip) * c.dr + j];
+    const C2 v = b[(size_t)a * (2 * c.dr) + (s ^ flip) * c.dr];
     C2 o = v;
     if (c.letter == 2) {  // Y: s=0 -> -i X^1, s=1 -> +i X^0
       if (s == 0) { o.x = v.y; o.y = -v.x; }
@@ -1003,41 +1023,56 @@ hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int 
 }
 
 // Closing traces: Tr(L_a R_b) = sum_{xy} L_a[x][y] R_b[y][x] = sum_x L_a[x] R^T_b[x]
-// with right environments stored transposed; computed in FP64 for every
-// (prefix, suffix) pair of a bond, real part only.
+// with right environments stored transposed; computed in FP64, real part
+// only, for the 64x64 tiles of (prefix, suffix) pairs that some string needs.
 template <typename C2>
-struct GramP {
+struct GramTileP {
   using T = double;
-  using Ctx = GramItem;
+  struct Ctx {
+    const void* const* lptr;
+    const void* const* rptr;
+    double* g;
+    int m, n, k, ldg;
+  };
+  using RowA = const C2*;
+  using ColB = const C2*;
   static constexpr bool A_CONTIG_K = true, B_CONTIG_N = false, REAL_ONLY = true;
   const GramItem* items;
-  __device__ Ctx context(int i) const { return items[i]; }
-  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
-    M = c.nl;
-    N = c.nr;
-    K = c.kdim;
+  const GramTile* tiles;
+  __device__ Ctx context(int i) const {
+    const GramTile t = tiles[i];
+    const GramItem b = items[t.item];
+    return Ctx{b.lptr + t.r0, b.rptr + t.c0, b.g + (size_t)t.r0 * b.nr + t.c0,
+               min(64, b.nl - t.r0), min(64, b.nr - t.c0), b.kdim, b.nr};
   }
-  __device__ static double2 loadA(const Ctx& c, int i, int k) {
-    const C2 v = ((const C2*)c.lptr[i])[k];
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.m;
+    N = c.n;
+    K = c.k;
+  }
+  __device__ static RowA rowA(const Ctx& c, int i) { return (const C2*)c.lptr[i]; }
+  __device__ static ColB colB(const Ctx& c, int j) { return (const C2*)c.rptr[j]; }
+  __device__ static double2 loadA(const Ctx&, RowA r, int, int k) {
+    const C2 v = r[k];
     return make_double2((double)v.x, (double)v.y);
   }
-  __device__ static double2 loadB(const Ctx& c, int k, int j) {
-    const C2 v = ((const C2*)c.rptr[j])[k];
+  __device__ static double2 loadB(const Ctx&, ColB b, int k, int) {
+    const C2 v = b[k];
     return make_double2((double)v.x, (double)v.y);
   }
   __device__ static void store(const Ctx& c, int i, int j, double re, double) {
-    c.g[(size_t)i * c.nr + j] = re;
+    c.g[(size_t)i * c.ldg + j] = re;
   }
 };
 
-hipError_t launch_gram(const GramItem* items_dev, int items, int max_nl, int max_nr, int elem_bytes,
-                       hipStream_t s) {
+hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles,
+                       int elem_bytes, hipStream_t s) {
   if (elem_bytes == 16) {
-    GramP<double2> p{items_dev};
-    return launch_cgemm<64, 64, 16>(p, items, max_nl, max_nr, s);
+    GramTileP<double2> p{items_dev, tiles_dev};
+    return launch_cgemm<64, 64, 16>(p, n_tiles, 64, 64, s);
   }
-  GramP<float2> p{items_dev};
-  return launch_cgemm<64, 64, 16>(p, items, max_nl, max_nr, s);
+  GramTileP<float2> p{items_dev, tiles_dev};
+  return launch_cgemm<64, 64, 16>(p, n_tiles, 64, 64, s);
 }
 
 __global__ void gather_kernel(const double* g, const int64_t* gidx, double* per_term, int64_t n) {

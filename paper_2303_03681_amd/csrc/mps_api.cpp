@@ -107,8 +107,8 @@ struct ExpectSetup {
     void* rroot;
   };
   std::vector<RootFill> roots;
-  size_t gram_off = 0;
-  int gram_items = 0, gram_max_nl = 0, gram_max_nr = 0;
+  size_t gram_off = 0, tiles_off = 0;
+  int gram_items = 0, gram_tiles = 0;
   double gram_flops = 0.0;
   int64_t n_updates = 0;
 };
@@ -803,34 +803,83 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   };
   build_pass(P.left, loff, true, ex.left_launches);
   build_pass(P.right, roff, false, ex.right_launches);
-  // ---- closes: per bond, unique left and right references
+  // ---- closes: per bond, unique left and right references, reordered so that
+  // the pairs strings need cluster into few 64x64 tiles of G (alternating
+  // barycentric sorts of the bipartite pair graph), and the list of tiles that
+  // hold at least one needed pair.
   std::vector<std::vector<int64_t>> by_bond(n + 1);
   for (int64_t k = 0; k < P.n_terms; ++k) by_bond[P.close_bond[k]].push_back(k);
   std::vector<GramItem> gram;
+  std::vector<GramTile> tiles;
   std::vector<int64_t> gidx((size_t)P.n_terms);
   size_t gtot = 0;
   std::vector<std::vector<const void*>> lptrs, rptrs;
   ex.gram_flops = 0.0;
-  ex.gram_max_nl = ex.gram_max_nr = 0;
   for (int c = 0; c <= n; ++c) {
     if (by_bond[c].empty()) continue;
     std::unordered_map<int32_t, int> li, ri;
-    std::vector<const void*> lp, rp;
+    std::vector<int32_t> lref, rref;
+    std::vector<int> pa, pb;  // pair endpoints (first-appearance indices)
     for (int64_t k : by_bond[c]) {
-      if (li.emplace(P.close_left[k], (int)lp.size()).second) lp.push_back(lref_ptr(P.close_left[k]));
-      if (ri.emplace(P.close_right[k], (int)rp.size()).second) rp.push_back(rref_ptr(P.close_right[k]));
+      auto a = li.emplace(P.close_left[k], (int)lref.size());
+      if (a.second) lref.push_back(P.close_left[k]);
+      auto b = ri.emplace(P.close_right[k], (int)rref.size());
+      if (b.second) rref.push_back(P.close_right[k]);
+      pa.push_back(a.first->second);
+      pb.push_back(b.first->second);
     }
-    for (int64_t k : by_bond[c])
-      gidx[k] = (int64_t)gtot + (int64_t)li[P.close_left[k]] * (int64_t)rp.size() + ri[P.close_right[k]];
-    GramItem gi{nullptr, nullptr, (double*)(uintptr_t)gtot, (int)lp.size(), (int)rp.size(),
-                D[c] * D[c]};
+    const int nl = (int)lref.size(), nr = (int)rref.size();
+    std::vector<int> lpos(nl), rpos(nr);
+    for (int i = 0; i < nl; ++i) lpos[i] = i;
+    for (int i = 0; i < nr; ++i) rpos[i] = i;
+    if (nl > 64 && nr > 64) {
+      std::vector<double> key;
+      std::vector<int> cnt, order;
+      for (int it = 0; it < 8; ++it) {
+        for (int side = 0; side < 2; ++side) {
+          const int cnt_n = side == 0 ? nl : nr;
+          key.assign(cnt_n, 0.0);
+          cnt.assign(cnt_n, 0);
+          for (size_t q = 0; q < pa.size(); ++q) {
+            const int self = side == 0 ? pa[q] : pb[q];
+            const int other = side == 0 ? rpos[pb[q]] : lpos[pa[q]];
+            key[self] += other;
+            cnt[self] += 1;
+          }
+          order.resize(cnt_n);
+          for (int i = 0; i < cnt_n; ++i) order[i] = i;
+          std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return key[x] * cnt[y] < key[y] * cnt[x];
+          });
+          std::vector<int>& pos = side == 0 ? lpos : rpos;
+          for (int i = 0; i < cnt_n; ++i) pos[order[i]] = i;
+        }
+      }
+    }
+    std::vector<const void*> lp(nl), rp(nr);
+    for (int i = 0; i < nl; ++i) lp[lpos[i]] = lref_ptr(lref[i]);
+    for (int i = 0; i < nr; ++i) rp[rpos[i]] = rref_ptr(rref[i]);
+    const int item = (int)gram.size();
+    std::vector<char> used((size_t)((nl + 63) / 64) * ((nr + 63) / 64), 0);
+    const int tcols = (nr + 63) / 64;
+    for (size_t q = 0; q < pa.size(); ++q) {
+      const int a = lpos[pa[q]], b = rpos[pb[q]];
+      gidx[by_bond[c][q]] = (int64_t)gtot + (int64_t)a * nr + b;
+      char& u = used[(size_t)(a / 64) * tcols + b / 64];
+      if (!u) {
+        u = 1;
+        tiles.push_back(GramTile{item, (a / 64) * 64, (b / 64) * 64});
+      }
+    }
+    GramItem gi{nullptr, nullptr, (double*)(uintptr_t)gtot, nl, nr, D[c] * D[c]};
     gram.push_back(gi);
     lptrs.push_back(std::move(lp));
     rptrs.push_back(std::move(rp));
-    gtot += (size_t)gi.nl * gi.nr;
-    ex.gram_flops += 4.0 * gi.nl * gi.nr * (double)gi.kdim;
-    ex.gram_max_nl = std::max(ex.gram_max_nl, gi.nl);
-    ex.gram_max_nr = std::max(ex.gram_max_nr, gi.nr);
+    gtot += (size_t)nl * nr;
+  }
+  for (const GramTile& t : tiles) {
+    const GramItem& b = gram[t.item];
+    ex.gram_flops += 4.0 * std::min(64, b.nl - t.r0) * std::min(64, b.nr - t.c0) * (double)b.kdim;
   }
   if (gtot > ex.gbuf_count || !ex.gbuf) {
     dfree(h, ex.gbuf);
@@ -846,6 +895,8 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   }
   ex.gram_items = (int)gram.size();
   ex.gram_off = put(nullptr, gram.size() * sizeof(GramItem));
+  ex.gram_tiles = (int)tiles.size();
+  ex.tiles_off = put(tiles.data(), tiles.size() * sizeof(GramTile));
   // terms
   const size_t T = (size_t)P.n_terms;
   if (T > ex.terms_cap || !ex.per_term) {
@@ -934,8 +985,9 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
     if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
   hipEvent_t b = nullptr, e = nullptr;
   if (h->timing && (st = timed_begin(h, h->ev_close, h->ev_close_used, b, e)) != MPS_OK) return st;
-  HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off), ex.gram_items,
-                         ex.gram_max_nl, ex.gram_max_nr, el, h->stream));
+  HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off),
+                         (const GramTile*)((char*)ex.desc + ex.tiles_off), ex.gram_tiles, el,
+                         h->stream));
   if (h->timing) {
     HIP_TRY(h, hipEventRecord(e, h->stream));
     h->tm.close_flops += ex.gram_flops;
