@@ -34,6 +34,13 @@ __device__ __forceinline__ double dpp_mov(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// A wave-uniform value moved to scalar registers (it is identical in all lanes).
+__device__ __forceinline__ double wave_uniform(double x) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
@@ -336,22 +343,29 @@ __device__ __forceinline__ void rv_from_lds(RegVec<E>& r, const double2* slot, i
   for (int k = 0; k < E; ++k) r.v[k] = slot[64 * k + lane];
 }
 
-// Algorithm 1's pair step on register vectors a (lower global index) and b.
+// Algorithm 1's pair step on register vectors x and y; the one with the lower
+// global index plays a_i.  One code path for both orientations:
+//   x' = c x + alpha y,  y' = c y + beta x  with (alpha, beta) =
+//   (s conj(e), -s e) if x is a_i, (-s e, s conj(e)) if y is a_i.
 template <int E>
-__device__ __forceinline__ bool jacobi_pair_reg(RegVec<E>& a, RegVec<E>& b, double eps, double floor) {
-  double bii = 0.0, bjj = 0.0, br = 0.0, bi = 0.0;
+__device__ __forceinline__ bool jacobi_pair_ordered(RegVec<E>& x, int gx, RegVec<E>& y, int gy,
+                                                    double eps, double floor) {
+  if (gx < 0 || gy < 0) return false;
+  double bxx = 0.0, byy = 0.0, br = 0.0, bi = 0.0;  // x^+ x, y^+ y, x^+ y
 #pragma unroll
   for (int k = 0; k < E; ++k) {
-    const double2 x = a.v[k], y = b.v[k];
-    bii += x.x * x.x + x.y * x.y;
-    bjj += y.x * y.x + y.y * y.y;
-    br += x.x * y.x + x.y * y.y;
-    bi += x.x * y.y - x.y * y.x;
+    const double2 a = x.v[k], b = y.v[k];
+    bxx += a.x * a.x + a.y * a.y;
+    byy += b.x * b.x + b.y * b.y;
+    br += a.x * b.x + a.y * b.y;
+    bi += a.x * b.y - a.y * b.x;
   }
-  bii = wave_sum(bii);
-  bjj = wave_sum(bjj);
+  bxx = wave_sum(bxx);
+  byy = wave_sum(byy);
   br = wave_sum(br);
   bi = wave_sum(bi);
+  const bool x_is_i = gx < gy;
+  const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
   const double mag = sqrt(br * br + bi * bi);
   if (!(mag > floor) || !(mag > eps * sqrt(bii * bjj))) return false;
   const double tau = (bii - bjj) / (2.0 * mag);
@@ -360,23 +374,20 @@ __device__ __forceinline__ bool jacobi_pair_reg(RegVec<E>& a, RegVec<E>& b, doub
   const double t = at > 1e100 ? sg * (0.5 / at) : sg / (at + sqrt(1.0 + tau * tau));
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = t * c;
-  const double er = br / mag, ei = bi / mag;
+  // e = b_ij / |b_ij| with b_ij = x^+ y (x is a_i) or y^+ x = conj(x^+ y)
+  const double er = br / mag, ei = x_is_i ? bi / mag : -bi / mag;
+  // s conj(e) and -s e
+  const double pr = s * er, pi = -s * ei, qr = -s * er, qi = -s * ei;
+  const double ar = wave_uniform(x_is_i ? pr : qr), ai = wave_uniform(x_is_i ? pi : qi);
+  const double brr = wave_uniform(x_is_i ? qr : pr), bri = wave_uniform(x_is_i ? qi : pi);
+  const double cu = wave_uniform(c);
 #pragma unroll
   for (int k = 0; k < E; ++k) {
-    const double2 x = a.v[k], y = b.v[k];
-    const double cbr = er * y.x + ei * y.y, cbi = er * y.y - ei * y.x;  // conj(e) b
-    const double ear = er * x.x - ei * x.y, eai = er * x.y + ei * x.x;  // e a
-    a.v[k] = make_double2(c * x.x + s * cbr, c * x.y + s * cbi);
-    b.v[k] = make_double2(c * y.x - s * ear, c * y.y - s * eai);
+    const double2 a = x.v[k], b = y.v[k];
+    x.v[k] = make_double2(cu * a.x + (ar * b.x - ai * b.y), cu * a.y + (ar * b.y + ai * b.x));
+    y.v[k] = make_double2(cu * b.x + (brr * a.x - bri * a.y), cu * b.y + (brr * a.y + bri * a.x));
   }
   return true;
-}
-
-template <int E>
-__device__ __forceinline__ bool jacobi_pair_ordered(RegVec<E>& x, int gx, RegVec<E>& y, int gy,
-                                                    double eps, double floor) {
-  if (gx < 0 || gy < 0) return false;
-  return gx < gy ? jacobi_pair_reg<E>(x, y, eps, floor) : jacobi_pair_reg<E>(y, x, eps, floor);
 }
 
 // Common prologue of the register kernels: which block pair this workgroup
@@ -462,7 +473,7 @@ __global__ __launch_bounds__(JW * 64) void jacobi_reg_full_kernel(const JacItem*
 // resident vector bp*8 + i; the travellers from block bq move one wave along
 // per inner round through 8 LDS slots.
 template <int E>
-__global__ __launch_bounds__(JW * 64) void jacobi_reg_cross_kernel(const JacItem* items, int max_pairs,
+__global__ __launch_bounds__(JW * 64, 4) void jacobi_reg_cross_kernel(const JacItem* items, int max_pairs,
                                                                    int round, int sweep,
                                                                    double eps_scale) {
   extern __shared__ double2 slots[];  // JW slots of 64 * E elements
