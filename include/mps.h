@@ -74,7 +74,7 @@ typedef struct {
                                 two-qubit gate: "truncate the small singular
                                 values below a certain threshold or simply
                                 reserve the largest few"); >= 0                   */
-  int32_t max_jacobi_sweeps; /* 0 = default (30)                                   */
+  int32_t max_jacobi_sweeps; /* 0 = default (60)                                   */
   const uint8_t* init_bits;  /* N bytes in {0,1}: initial product state; NULL = 0s */
   void* stream;              /* hipStream_t to enqueue on; NULL = library-owned    */
   size_t hbm_budget_bytes;   /* 0 = unlimited; otherwise device bytes the handle

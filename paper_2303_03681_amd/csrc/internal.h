@@ -61,7 +61,8 @@ struct TruncItem {        // Eq. (Bl): out (2Dl x k) = C (2Dl x 2Dr) * conj(V)^T
   const double2* v;       // [s][a][r], k rows per s
   double2* out;
   const double* scale;
-  int rows, dr, k;        // rows = 2Dl
+  const int* k_dev;       // if not null, k is read from here (written by finalize)
+  int rows, dr, k;        // rows = 2Dl; k is the upper bound when k_dev is set
 };
 
 // ---------------------------------------------------------------- canonical form

@@ -689,7 +689,11 @@ struct TruncP {
   using Ctx = TruncItem;
   static constexpr bool A_CONTIG_K = true, B_CONTIG_N = false, REAL_ONLY = false;
   const TruncItem* items;
-  __device__ Ctx context(int i) const { return items[i]; }
+  __device__ Ctx context(int i) const {
+    TruncItem t = items[i];
+    if (t.k_dev) t.k = min(t.k, *t.k_dev);
+    return t;
+  }
   __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
     M = c.rows;
     N = c.k;

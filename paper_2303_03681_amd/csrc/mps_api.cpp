@@ -7,7 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -34,7 +36,7 @@ mps_status fail(mps_status st, const std::string& msg) {
 
 constexpr double kEpsScale = 1.1102230246251565e-16;  // 2^-53: eps = m * 2^-53 (Algorithm 1)
 constexpr double kCanonCutoff = 1e-14;                  // round-off singular values only
-constexpr int kDefaultSweeps = 30;
+constexpr int kDefaultSweeps = 60;
 constexpr int kMaxBond = 512;                           // finalize handles 2D <= 1024 vectors
 
 int cap_dim(int b, int n, int D) {
@@ -49,7 +51,8 @@ double now_ms() {
       .count();
 }
 
-size_t g_lds_budget = 0;  // dynamic LDS the Jacobi kernels may use
+size_t g_lds_budget = 0;  // dynamic LDS the Jacobi kernels may use (set once per process)
+std::mutex g_lds_mutex;
 
 }  // namespace
 
@@ -61,7 +64,7 @@ struct mps_psum {
   uint64_t serial;
 };
 
-static uint64_t g_plan_serial = 1;
+static std::atomic<uint64_t> g_plan_serial{1};
 
 // ----------------------------------------------------------------------------
 // handle
@@ -221,6 +224,7 @@ mps_status check_handle(mps_state* h) {
 }
 
 mps_status ensure_lds(mps_state* h) {
+  std::lock_guard<std::mutex> lock(g_lds_mutex);
   if (g_lds_budget) return MPS_OK;
   int dev = 0, v = 0;
   HIP_TRY(h, hipGetDevice(&dev));
@@ -313,7 +317,8 @@ void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   for (JacItem it : all) {
     const size_t per_vec = (size_t)it.m * sizeof(double2);
     const int nloc = (it.n + 1) & ~1;
-    if (nloc <= 2 * kRegBlock && (size_t)it.n * per_vec <= budget) {
+    if (nloc <= 1024 && (size_t)it.n * per_vec <= budget &&
+        (nloc <= 2 * kRegBlock || it.m > kRegMaxLen || (size_t)it.n * it.m <= 64 * 64)) {
       it.wblk = nloc;
       it.nb = 1;
       jp.single.push_back(it);
@@ -438,7 +443,8 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
   std::vector<MixItem> mx(items);
   std::vector<JacItem> jc(items);
   std::vector<FinItem> fn(items);
-  int max_rows = 0, max_cols = 0, max_dldr = 0;
+  std::vector<TruncItem> tr(items);
+  int max_rows = 0, max_cols = 0, max_dldr = 0, max_k = 0;
   for (int b = 0; b < items; ++b) {
     const int q = qs[b];
     const int dl = h->dims[q], dm = h->dims[q + 1], dr = h->dims[q + 2];
@@ -446,32 +452,36 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
       return fail(MPS_ERR_STATE, "internal: workspace too small");
     double2* c = h->ws_c + (size_t)b * h->ws_stride;
     double2* w = h->ws_w + (size_t)b * h->ws_stride;
+    const int capk = std::min(h->cap[q + 1], std::min(2 * dl, 2 * dr));
     th[b] = ThetaItem{h->cur(q), h->cur(q + 1), c, dl, dm, dr};
     mx[b] = MixItem{c, w, h->lcur(q), h->d_gates + (size_t)gidx[b] * 16, h->d_fro2 + b, dl, dr};
     jc[b] = JacItem{w, h->d_fro2 + b, h->d_rot + b, h->d_sweeps + b, 2 * dl, 2 * dr, 0, 0, items};
-    const int capk = h->cap[q + 1];
     fn[b] = FinItem{w, h->spare(q + 1), h->lspare(q + 1), h->d_k + b, h->d_scale + b,
                     h->d_disc + b, h->d_status + b, 2 * dl, 2 * dr, capk, h->cutoff, FIN_GATE};
+    // Eq. (Bl) with k read on the device: it is enqueued before the host
+    // learns k; the result stays in the spare buffers until committed.
+    tr[b] = TruncItem{c, h->spare(q + 1), h->spare(q), h->d_scale + b, h->d_k + b, 2 * dl, dr, capk};
     max_rows = std::max(max_rows, 2 * dl);
     max_cols = std::max(max_cols, 2 * dr);
     max_dldr = std::max(max_dldr, dl * dr);
+    max_k = std::max(max_k, capk);
   }
-  size_t off = 0;
-  auto place = [&](size_t bytes) {
-    const size_t o = off;
-    off += (bytes + 255) & ~(size_t)255;
+  // one upload for all descriptors of the batch
+  std::vector<char> blob;
+  auto place = [&](const void* src, size_t bytes) {
+    const size_t o = blob.size();
+    blob.resize(o + ((bytes + 255) & ~(size_t)255));
+    std::memcpy(blob.data() + o, src, bytes);
     return o;
   };
-  const size_t o_th = place(sizeof(ThetaItem) * items);
-  const size_t o_mx = place(sizeof(MixItem) * items);
-  const size_t o_fn = place(sizeof(FinItem) * items);
-  const size_t o_tr = place(sizeof(TruncItem) * items);
-  const size_t o_jac = off;
-  if ((st = ensure_desc(h, off + 2 * sizeof(JacItem) * items + 512)) != MPS_OK) return st;
+  const size_t o_th = place(th.data(), sizeof(ThetaItem) * items);
+  const size_t o_mx = place(mx.data(), sizeof(MixItem) * items);
+  const size_t o_fn = place(fn.data(), sizeof(FinItem) * items);
+  const size_t o_tr = place(tr.data(), sizeof(TruncItem) * items);
+  const size_t o_jac = blob.size();
+  if ((st = ensure_desc(h, o_jac + 3 * sizeof(JacItem) * items + 512)) != MPS_OK) return st;
   char* d = (char*)h->d_desc;
-  if ((st = upload(h, d + o_th, th.data(), sizeof(ThetaItem) * items)) != MPS_OK) return st;
-  if ((st = upload(h, d + o_mx, mx.data(), sizeof(MixItem) * items)) != MPS_OK) return st;
-  if ((st = upload(h, d + o_fn, fn.data(), sizeof(FinItem) * items)) != MPS_OK) return st;
+  if ((st = upload(h, d, blob.data(), blob.size())) != MPS_OK) return st;
   HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double) * items, h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * items * h->max_sweeps, h->stream));
   HIP_TRY(h, launch_theta((const ThetaItem*)(d + o_th), items, max_rows, max_cols, h->stream));
@@ -479,6 +489,7 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
   std::vector<int> sweeps;
   if ((st = run_jacobi(h, jc, o_jac, sweeps)) != MPS_OK) return st;
   HIP_TRY(h, launch_finalize((const FinItem*)(d + o_fn), items, h->stream));
+  HIP_TRY(h, launch_trunc((const TruncItem*)(d + o_tr), items, max_rows, max_k, h->stream));
   std::vector<int> k(items), status(items);
   std::vector<double> disc(items);
   HIP_TRY(h, hipMemcpyAsync(k.data(), h->d_k, sizeof(int) * items, hipMemcpyDeviceToHost, h->stream));
@@ -495,19 +506,9 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
     if (status[b] != 0)
       return fail(MPS_ERR_NONFINITE, "non-finite or zero singular values (gate on qubit " +
                                          std::to_string(qs[b]) + ")");
-    if (k[b] < 1 || k[b] > h->cap[qs[b] + 1])
+    if (k[b] < 1 || k[b] > tr[b].k)
       return fail(MPS_ERR_STATE, "internal: kept rank out of range");
   }
-  std::vector<TruncItem> tr(items);
-  int max_k = 0;
-  for (int b = 0; b < items; ++b) {
-    const int q = qs[b];
-    tr[b] = TruncItem{h->ws_c + (size_t)b * h->ws_stride, h->spare(q + 1), h->spare(q),
-                      h->d_scale + b, 2 * h->dims[q], h->dims[q + 2], k[b]};
-    max_k = std::max(max_k, k[b]);
-  }
-  if ((st = upload(h, d + o_tr, tr.data(), sizeof(TruncItem) * items)) != MPS_OK) return st;
-  HIP_TRY(h, launch_trunc((const TruncItem*)(d + o_tr), items, max_rows, max_k, h->stream));
   for (int b = 0; b < items; ++b) {
     const int q = qs[b];
     h->site_cur[q] ^= 1;
@@ -603,7 +604,7 @@ mps_status canonicalize_impl(mps_state* h) {
     if ((st = sync(h)) != MPS_OK) return st;
     if (status != 0) return fail(MPS_ERR_NONFINITE, "non-finite state in canonicalisation");
     if (q > 0) {
-      TruncItem ti{W0, h->spare(q), Tn, h->d_one, dl, rr, k};
+      TruncItem ti{W0, h->spare(q), Tn, h->d_one, nullptr, dl, rr, k};
       if ((st = upload(h, d + 2048, &ti, sizeof(ti))) != MPS_OK) return st;
       HIP_TRY(h, launch_trunc((const TruncItem*)(d + 2048), 1, dl, k, h->stream));
     } else {
@@ -726,7 +727,26 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   };
   if ((st = grow(&ex.pool, ex.pool_bytes, pool * el)) != MPS_OK) return st;
   if ((st = grow(&ex.sites, ex.sites_bytes, site_elems * el)) != MPS_OK) return st;
-  const size_t x_elems = std::min<size_t>(x_budget_elems, xmax_per * (size_t)chunk_cap);
+  // X space actually needed: the largest chunk of distinct parents times its
+  // per-parent size, over every site of both passes.
+  auto x_need = [&](const std::vector<TrieNode>& nodes) {
+    size_t need = 0;
+    size_t i = 0;
+    while (i < nodes.size()) {
+      const int site = nodes[i].site;
+      const size_t xper = (size_t)D[site] * 2 * D[site + 1];
+      size_t distinct = 0;
+      int32_t last = INT32_MIN;
+      for (; i < nodes.size() && nodes[i].site == site; ++i)
+        if (nodes[i].parent != last) {
+          last = nodes[i].parent;
+          ++distinct;
+        }
+      need = std::max(need, std::min<size_t>(distinct, (size_t)chunk_cap) * xper);
+    }
+    return need;
+  };
+  const size_t x_elems = std::max<size_t>(1, std::max(x_need(P.left), x_need(P.right)));
   if ((st = grow(&ex.xbuf, ex.xbuf_bytes, x_elems * el)) != MPS_OK) return st;
   char* poolp = (char*)ex.pool;
   char* sitep = (char*)ex.sites;
@@ -1238,7 +1258,7 @@ mps_status mps_pauli_sum_create(int32_t n_qubits, int64_t n_terms, const uint8_t
   std::string err;
   if (!build_pauli_plan(n_qubits, n_terms, codes, coeffs, p->plan, err))
     return fail(MPS_ERR_ARG, err);
-  p->serial = g_plan_serial++;
+  p->serial = g_plan_serial.fetch_add(1);
   *out = p.release();
   return MPS_OK;
 }

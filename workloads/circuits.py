@@ -155,9 +155,24 @@ def _generator_strings(n_qubits, orbs_left, orbs_right):
     return codes, vals.imag.copy()
 
 
-def uccsd_gates(n_qubits: int, n_electrons: int, theta: np.ndarray) -> list[Gate]:
-    """First-order Trotterised UCCSD: prod_ex prod_k exp(i theta_ex c_k P_k)."""
+def window_excitations(n_qubits: int, n_electrons: int, window: int = 5):
+    """UCCSD excitations whose spatial orbitals all lie within `window`
+    consecutive orbitals (Methods, ansatz for hydrogen chains: operators built
+    on every 5 consecutive orbitals)."""
     singles, doubles = uccsd_excitations(n_qubits, n_electrons)
+    def ok(*spin_orbitals):
+        sp = [o // 2 for o in spin_orbitals]
+        return max(sp) - min(sp) < window
+    return [e for e in singles if ok(*e)], [e for e in doubles if ok(*e)]
+
+
+def uccsd_gates(n_qubits: int, n_electrons: int, theta: np.ndarray, window: int | None = None) -> list[Gate]:
+    """First-order Trotterised UCCSD: prod_ex prod_k exp(i theta_ex c_k P_k).
+    With `window`, only the excitations of window_excitations are used."""
+    if window is None:
+        singles, doubles = uccsd_excitations(n_qubits, n_electrons)
+    else:
+        singles, doubles = window_excitations(n_qubits, n_electrons, window)
     exc = [((a,), (i,)) for (i, a) in singles] + [((a, b), (i, j)) for (i, j, a, b) in doubles]
     theta = np.asarray(theta, dtype=float)
     assert theta.size == len(exc), (theta.size, len(exc))
@@ -169,8 +184,11 @@ def uccsd_gates(n_qubits: int, n_electrons: int, theta: np.ndarray) -> list[Gate
     return gates
 
 
-def uccsd_n_params(n_qubits: int, n_electrons: int) -> int:
-    s, d = uccsd_excitations(n_qubits, n_electrons)
+def uccsd_n_params(n_qubits: int, n_electrons: int, window: int | None = None) -> int:
+    if window is None:
+        s, d = uccsd_excitations(n_qubits, n_electrons)
+    else:
+        s, d = window_excitations(n_qubits, n_electrons, window)
     return len(s) + len(d)
 
 
