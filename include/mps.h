@@ -101,11 +101,21 @@ mps_status mps_apply_gate(mps_handle h, int32_t q0, int32_t q1, const double* u)
 
 /* Apply n gates in order.  u_packed holds 32 doubles per gate (a 4x4 complex
  * matrix; a 2x2 gate uses the first 8).  Consecutive two-qubit gates on
- * disjoint bonds are processed as one batch (one batched SVD).  On error the
- * gates before the failing batch stay applied; *n_done (may be NULL)
- * receives the number of gates applied. */
+ * disjoint bonds are processed as one batch (one batched SVD).  Where at most
+ * four such gates form a batch and both outer bonds of each have capacity
+ * min(max_bond, 2^min(b, N-b)) <= 64 (chains of dependent gates, as in
+ * Pauli-exponential ladders), each gate runs as one fused device step and the
+ * run is queued without host round trips.  On error the gates before the
+ * failing gate (fused) or batch stay applied; *n_done (may be NULL) receives
+ * the number of gates applied.  The result does not depend on which path a
+ * gate takes beyond rounding. */
 mps_status mps_apply_gates(mps_handle h, int64_t n, const int32_t* q0, const int32_t* q1,
                            const double* u_packed, int64_t* n_done);
+
+/* Allow (enabled != 0, the default) or forbid the fused single-gate path of
+ * mps_apply_gates; with it forbidden every two-qubit gate takes the batched
+ * path.  For comparisons and tests. */
+mps_status mps_set_fused_gates(mps_handle h, int32_t enabled);
 
 /* Restore the exact right-canonical gauge (Eq. rc), exact Schmidt values on
  * every bond and unit norm: a left-to-right orthonormalisation sweep followed

@@ -91,6 +91,7 @@ _SIGS = {
     "mps_import_site": [_P, _I32, _I32, _I32, _P, _P],
     "mps_jacobi_svd": [_I32, _I32, _P, _P, _P, _P],
     "mps_set_timing": [_P, _I32],
+    "mps_set_fused_gates": [_P, _I32],
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
     "mps_selftest_mfma": [_P],
@@ -226,7 +227,11 @@ class Mps:
         if u.size != 32 * q0.size or q1.size != q0.size:
             raise ValueError("u_packed must hold 32 doubles per gate")
         done = C.c_int64()
-        _check(_lib.mps_apply_gates(self._h, q0.size, _ptr(q0), _ptr(q1), _ptr(u), C.byref(done)))
+        try:
+            _check(_lib.mps_apply_gates(self._h, q0.size, _ptr(q0), _ptr(q1), _ptr(u), C.byref(done)))
+        except MpsError as err:
+            err.n_done = done.value  # gates applied before the failure
+            raise
         return done.value
 
     def canonicalize(self):
@@ -270,6 +275,10 @@ class Mps:
         return (e.value, out) if per_term else e.value
 
     # -- instrumentation ----------------------------------------------------
+    def set_fused_gates(self, on: bool = True):
+        """Allow or forbid the fused single-gate path of apply_gates."""
+        _check(_lib.mps_set_fused_gates(self._h, 1 if on else 0))
+
     def set_timing(self, on: bool = True):
         _check(_lib.mps_set_timing(self._h, 1 if on else 0))
 

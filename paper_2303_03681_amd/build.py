@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_NAME = "libmps_hip.so"
 LIB_PATH = os.path.join(PKG_DIR, LIB_NAME)
 
-SOURCES = ["kernels.hip", "mps_api.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "gate_fused.hip", "mps_api.cpp", "planner.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,644 @@
+// One two-qubit gate per workgroup, with the bond dimensions read from and
+// written to device memory, so consecutive gates of a circuit queue on the
+// stream without the host learning each new rank.  For bonds whose two-site
+// matrix C~ is at most 128 x 128 (bond capacity <= 64 on both sides).
+//
+//   Eq. (C)   C = sum_{i'j'} Q B_q^{i'} B_{q+1}^{j'}          -> scratch (L2-resident)
+//   Eq. (C~)  rows of lambda C, held in registers
+//   Alg. 1    one-sided Jacobi on those rows until a sweep makes no rotation
+//   Eq. (svd) sigma = row norms, stable descending order, truncation rank k
+//   Eq. (Bl)  B_{q+1} <- V_k^+,  B_q <- C V_k / ||sigma_1..k||,  lambda <- sigma_k / ||sigma_1..k||
+//
+// Jacobi layout: 8 waves; wave w holds two blocks of 8 rows ("top" and
+// "bottom"), each lane E elements of every row (e = lane + 64 k).  A sweep is
+// a round-robin over the nb blocks: in round r the blocks at positions
+// w and nb-1-w meet in wave w (position 0 fixed, the others advance by one),
+// so every block pair meets once per sweep; round 0 also pairs the rows
+// inside each block.  Within a wave the 64 cross pairs of its two blocks run
+// as 8 sub-rounds of 8 disjoint pairs whose reductions interleave.  Between
+// rounds, blocks move through LDS in two phases (tops, then bottoms), so at
+// most nb/2 block slots are needed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <utility>
+
+#include "internal.h"
+#include "wave_ops.h"
+
+namespace mps {
+
+namespace {
+
+constexpr int FW = 8;      // waves per workgroup
+constexpr int FB = 8;      // rows per block
+constexpr int FMAXN = 128; // rows (2 D_l) and row length (2 D_r) limit
+constexpr int FVS = 65;    // LDS row stride (double2) of the staged V^+ (bank spread)
+
+// Position p of the block round-robin in round r holds block pos_id(p, r).
+__device__ __forceinline__ int pos_id(int p, int r, int nb) {
+  return p == 0 ? 0 : 1 + ((p - 1 + r) % (nb - 1));
+}
+
+// Player at position p in sub-round s of the 8-player circle method.
+constexpr int rr8(int p, int s) { return p == 0 ? 0 : 1 + ((p - 1 + s) % 7); }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a < b ? b : a; }
+
+template <int E>
+__device__ __forceinline__ void pair_partials(const double2 (&x)[E], const double2 (&y)[E],
+                                              double* acc) {
+  double xx = 0.0, yy = 0.0, re = 0.0, im = 0.0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 a = x[k], b = y[k];
+    xx += a.x * a.x + a.y * a.y;
+    yy += b.x * b.x + b.y * b.y;
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  acc[0] = xx;
+  acc[1] = yy;
+  acc[2] = re;
+  acc[3] = im;
+}
+
+struct Rot {
+  double c, ar, ai, br, bi;  // x' = c x + (ar + i ai) y,  y' = c y + (br + i bi) x
+};
+
+// Algorithm 1's rotation for the reduced (x^+x, y^+y, Re x^+y, Im x^+y) of
+// one pair, in this lane; the row with the lower index plays a_i.  Returns
+// false when the pair is already orthogonal to the tolerance
+// (|b_ij| <= eps sqrt(b_ii b_jj) or <= floor).
+__device__ __forceinline__ bool pair_rot_lane(const double* acc, bool x_is_i, double eps,
+                                              double floor, Rot& rt) {
+  const double bxx = acc[0], byy = acc[1], br = acc[2], bi = acc[3];
+  const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
+  const double mag = sqrt(br * br + bi * bi);
+  if (!(mag > floor) || !(mag > eps * sqrt(bii * bjj))) return false;
+  const double tau = (bii - bjj) / (2.0 * mag);
+  const double at = fabs(tau);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  const double t = at > 1e100 ? sg * (0.5 / at) : sg / (at + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = t * c;
+  const double er = br / mag, ei = x_is_i ? bi / mag : -bi / mag;
+  // a_i' = c a_i + s conj(e) a_j,  a_j' = c a_j - s e a_i
+  const double pr = s * er, pi = -s * ei, qr = -s * er, qi = -s * ei;
+  rt.c = c;
+  rt.ar = x_is_i ? pr : qr;
+  rt.ai = x_is_i ? pi : qi;
+  rt.br = x_is_i ? qr : pr;
+  rt.bi = x_is_i ? qi : pi;
+  return true;
+}
+
+template <int E>
+__device__ __forceinline__ void pair_apply(double2 (&x)[E], double2 (&y)[E], const Rot& rt) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 a = x[k], b = y[k];
+    x[k] = make_double2(rt.c * a.x + (rt.ar * b.x - rt.ai * b.y), rt.c * a.y + (rt.ar * b.y + rt.ai * b.x));
+    y[k] = make_double2(rt.c * b.x + (rt.br * a.x - rt.bi * a.y), rt.c * b.y + (rt.br * a.y + rt.bi * a.x));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eight pairs at a time.  The 32 per-lane partial sums (x^+x, y^+y, Re x^+y,
+// Im x^+y of 8 pairs) are reduce-scattered over the wave (each lane ends with
+// one full sum instead of all 32), gathered so that every lane holds the four
+// sums of one pair, and Algorithm 1's rotation of that pair is computed lane-
+// parallel (8 pairs per instruction stream); the coefficients then go to
+// scalar registers for the vector updates.
+
+// Which register block (0 top, 1 bottom) and row each pair of a group uses.
+template <int S>
+struct CrossPairs {  // (top[i], bottom[(i + S) % 8])
+  static constexpr int xa(int) { return 0; }
+  static constexpr int xr(int i) { return i; }
+  static constexpr int ya(int) { return 1; }
+  static constexpr int yr(int i) { return (i + S) % FB; }
+};
+
+template <int S>
+struct IntraPairs {  // circle-method sub-round S inside the top (i < 4) and bottom block
+  static constexpr int xa(int i) { return i < 4 ? 0 : 1; }
+  static constexpr int xr(int i) { return cmin(rr8(i % 4, S), rr8(7 - i % 4, S)); }
+  static constexpr int ya(int i) { return xa(i); }
+  static constexpr int yr(int i) { return cmax(rr8(i % 4, S), rr8(7 - i % 4, S)); }
+};
+
+template <int E, int A>
+__device__ __forceinline__ double2 (&blk(double2 (&T)[FB][E], double2 (&B)[FB][E]))[FB][E] {
+  if constexpr (A == 0) return T;
+  else return B;
+}
+
+// One reduce-scatter stage: keep the half of v selected by this lane's bit,
+// add the partner's copy of it (the partner keeps the other half).
+template <int H>
+__device__ __forceinline__ double rs_pick(const double (&v)[2 * H], int j, bool hi, bool send) {
+  return (hi != send) ? v[H + j] : v[j];
+}
+
+template <int PAT>
+__device__ __forceinline__ double swizzle(double x) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), PAT);
+  return __hiloint2double(hi, lo);
+}
+// ds_swizzle bit mode: lane' = ((lane & and) | or) ^ xor within 32 lanes
+constexpr int swz(int x) { return 0x1F | (x << 10); }
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+template <int E, class P, int I>
+__device__ __forceinline__ void partials_one(double2 (&T)[FB][E], double2 (&B)[FB][E], double (&v)[32]) {
+  double2 (&X)[FB][E] = blk<E, P::xa(I)>(T, B);
+  double2 (&Y)[FB][E] = blk<E, P::ya(I)>(T, B);
+  double acc[4];
+  pair_partials<E>(X[P::xr(I)], Y[P::yr(I)], acc);
+  v[I] = acc[0];
+  v[8 + I] = acc[1];
+  v[16 + I] = acc[2];
+  v[24 + I] = acc[3];
+}
+
+template <int E, class P, int I>
+__device__ __forceinline__ int apply_one(double2 (&T)[FB][E], double2 (&B)[FB][E], uint64_t act,
+                                         const Rot& mine) {
+  // lane holding pair I after the reduce-scatter: bits (b1 b0 b4) = I, b2 = b3 = 0
+  constexpr int L = (((I >> 2) & 1) << 1) | ((I >> 1) & 1) | ((I & 1) << 4);
+  if (!((act >> L) & 1)) return 0;
+  Rot rt;
+  rt.c = readlane_d(mine.c, L);
+  rt.ar = readlane_d(mine.ar, L);
+  rt.ai = readlane_d(mine.ai, L);
+  rt.br = readlane_d(mine.br, L);
+  rt.bi = readlane_d(mine.bi, L);
+  double2 (&X)[FB][E] = blk<E, P::xa(I)>(T, B);
+  double2 (&Y)[FB][E] = blk<E, P::ya(I)>(T, B);
+  pair_apply<E>(X[P::xr(I)], Y[P::yr(I)], rt);
+  return 1;
+}
+
+template <int E, class P, int... I>
+__device__ __forceinline__ int rot8_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], bool x_is_i,
+                                         double eps, double floor, int lane,
+                                         std::integer_sequence<int, I...>) {
+  double v[32];  // v[8c + i]: component c of pair i
+  (partials_one<E, P, I>(T, B, v), ...);
+  // reduce-scatter: lane bits 3, 2, 1, 0 by DPP, then 4; value index bits
+  // (4, 3, 2, 1, 0) <- lane bits (3, 2, 1, 0, 4)
+  double v16[16], v8[8], v4[4], v2[2];
+  {
+    const bool hi = (lane >> 3) & 1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      v16[j] = rs_pick<16>(v, j, hi, false) + dpp_mov<0x140>(rs_pick<16>(v, j, hi, true));
+  }
+  {
+    const bool hi = (lane >> 2) & 1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      v8[j] = rs_pick<8>(v16, j, hi, false) + dpp_mov<0x141>(rs_pick<8>(v16, j, hi, true));
+  }
+  {
+    const bool hi = (lane >> 1) & 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v4[j] = rs_pick<4>(v8, j, hi, false) + dpp_mov<0x4E>(rs_pick<4>(v8, j, hi, true));
+  }
+  {
+    const bool hi = lane & 1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      v2[j] = rs_pick<2>(v4, j, hi, false) + dpp_mov<0xB1>(rs_pick<2>(v4, j, hi, true));
+  }
+  double x;
+  {
+    const bool hi = (lane >> 4) & 1;
+    x = rs_pick<1>(v2, 0, hi, false) + swizzle<swz(16)>(rs_pick<1>(v2, 0, hi, true));
+  }
+  x += __shfl_xor(x, 32, 64);  // the same bits in lanes l and l ^ 32
+  // gather the four components c = (lane bit 3, lane bit 2) of this lane's pair
+  const double x4 = swizzle<swz(4)>(x);
+  const double x8 = swizzle<swz(8)>(x);
+  const double x12 = swizzle<swz(12)>(x);
+  const int c = ((lane >> 2) & 3);
+  const double cc0 = c == 0 ? x : c == 1 ? x4 : c == 2 ? x8 : x12;
+  const double cc1 = c == 1 ? x : c == 0 ? x4 : c == 3 ? x8 : x12;
+  const double cc2 = c == 2 ? x : c == 3 ? x4 : c == 0 ? x8 : x12;
+  const double cc3 = c == 3 ? x : c == 2 ? x4 : c == 1 ? x8 : x12;
+  const double acc[4] = {cc0, cc1, cc2, cc3};
+  Rot mine{1.0, 0.0, 0.0, 0.0, 0.0};
+  const bool a = pair_rot_lane(acc, x_is_i, eps, floor, mine);
+  const uint64_t act = __ballot(a);
+  if (act == 0) return 0;
+  return (apply_one<E, P, I>(T, B, act, mine) + ...);
+}
+
+template <int E, class P>
+__device__ __forceinline__ int rot8(double2 (&T)[FB][E], double2 (&B)[FB][E], bool x_is_i,
+                                    double eps, double floor, int lane) {
+  return rot8_impl<E, P>(T, B, x_is_i, eps, floor, lane, std::make_integer_sequence<int, 8>{});
+}
+
+template <int E, int... S>
+__device__ __forceinline__ int cross_all_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], bool top_is_i,
+                                              double eps, double floor, int lane,
+                                              std::integer_sequence<int, S...>) {
+  return (rot8<E, CrossPairs<S>>(T, B, top_is_i, eps, floor, lane) + ...);
+}
+
+template <int E, int... S>
+__device__ __forceinline__ int intra_all_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], double eps,
+                                              double floor, int lane, std::integer_sequence<int, S...>) {
+  return (rot8<E, IntraPairs<S>>(T, B, true, eps, floor, lane) + ...);
+}
+
+template <int E>
+__device__ __forceinline__ int cross_all(double2 (&T)[FB][E], double2 (&B)[FB][E], bool top_is_i,
+                                         double eps, double floor, int lane) {
+  return cross_all_impl<E>(T, B, top_is_i, eps, floor, lane, std::make_integer_sequence<int, 8>{});
+}
+
+template <int E>
+__device__ __forceinline__ int intra_all(double2 (&T)[FB][E], double2 (&B)[FB][E], double eps,
+                                         double floor, int lane) {
+  return intra_all_impl<E>(T, B, eps, floor, lane, std::make_integer_sequence<int, 7>{});
+}
+
+template <int E>
+__device__ __forceinline__ void blk_store(const double2 (&X)[FB][E], double2* slot, int lane) {
+#pragma unroll
+  for (int t = 0; t < FB; ++t)
+#pragma unroll
+    for (int k = 0; k < E; ++k) slot[(t * E + k) * 64 + lane] = X[t][k];
+}
+
+template <int E>
+__device__ __forceinline__ void blk_load(double2 (&X)[FB][E], const double2* slot, int lane) {
+#pragma unroll
+  for (int t = 0; t < FB; ++t)
+#pragma unroll
+    for (int k = 0; k < E; ++k) X[t][k] = slot[(t * E + k) * 64 + lane];
+}
+
+// Advance the round-robin by one round: position p <- position p + 1 for
+// p = 1 .. nb-2, position nb-1 <- position 1.  In waves: top(w) <- top(w+1)
+// for 1 <= w <= nwa-2, top(nwa-1) <- bottom(nwa-1), bottom(w) <- bottom(w-1)
+// for w >= 1, bottom(0) <- top(1); top(0) stays.  Every wave of the
+// workgroup calls this (it holds the barriers).
+template <int E>
+__device__ __forceinline__ void advance(double2 (&T)[FB][E], double2 (&B)[FB][E], double2* xs,
+                                        int wv, int nwa, int lane) {
+  constexpr int SLOT = FB * 64 * E;
+  __syncthreads();
+  if (wv >= 1 && wv < nwa) blk_store<E>(T, xs + (size_t)(wv - 1) * SLOT, lane);
+  __syncthreads();
+  if (wv >= 1 && wv <= nwa - 2) blk_load<E>(T, xs + (size_t)wv * SLOT, lane);
+  if (wv == nwa - 1) {
+#pragma unroll
+    for (int t = 0; t < FB; ++t)
+#pragma unroll
+      for (int k = 0; k < E; ++k) T[t][k] = B[t][k];
+  }
+  __syncthreads();
+  if (wv <= nwa - 2) blk_store<E>(B, xs + (size_t)(wv + 1) * SLOT, lane);
+  __syncthreads();
+  if (wv >= 1 && wv < nwa) blk_load<E>(B, xs + (size_t)wv * SLOT, lane);
+  if (wv == 0) blk_load<E>(B, xs, lane);
+}
+
+__device__ __forceinline__ void set_status(const FusedGate& g, int code) {
+  g.status[1] = g.gate;
+  __threadfence();
+  g.status[0] = code;
+}
+
+}  // namespace
+
+template <int E>
+__global__ __launch_bounds__(FW * 64) void gate2q_fused_kernel(FusedGate g) {
+  extern __shared__ double2 xs[];  // block slots, then the staged V^+
+  __shared__ double s_sig[FMAXN];
+  __shared__ int s_perm[FMAXN];
+  __shared__ int s_rank[FMAXN];
+  __shared__ double s_part[FW];
+  __shared__ int s_rot[2];
+  __shared__ int s_k;
+  __shared__ double s_inv;
+  __shared__ int s_ok;
+
+  if (g.status[0] != 0) return;  // an earlier gate of this run failed: apply nothing
+  const int Dl = g.dims[g.q], Dm = g.dims[g.q + 1], Dr = g.dims[g.q + 2];
+  const int n = 2 * Dl, m = 2 * Dr;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double2* C = g.c;
+
+  // ---- Eq. (C): C[(i,a)][(j,r)] = sum_{i'j'} Q[2i+j][2i'+j'] (B_q^{i'} B_{q+1}^{j'})[a][r]
+  double2 u[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) u[i] = g.u[i];
+  for (int idx = threadIdx.x; idx < Dl * Dr; idx += FW * 64) {
+    const int a = idx / Dr, r = idx - a * Dr;
+    const double2* x0 = g.bq + (size_t)a * Dm;
+    const double2* x1 = g.bq + (size_t)(Dl + a) * Dm;
+    const double2* y0 = g.bq1 + r;
+    const double2* y1 = g.bq1 + (size_t)Dm * Dr + r;
+    double2 t[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                    make_double2(0.0, 0.0)};
+    for (int b = 0; b < Dm; ++b) {
+      const double2 a0 = x0[b], a1 = x1[b], b0 = y0[(size_t)b * Dr], b1 = y1[(size_t)b * Dr];
+      t[0].x += a0.x * b0.x - a0.y * b0.y; t[0].y += a0.x * b0.y + a0.y * b0.x;
+      t[1].x += a0.x * b1.x - a0.y * b1.y; t[1].y += a0.x * b1.y + a0.y * b1.x;
+      t[2].x += a1.x * b0.x - a1.y * b0.y; t[2].y += a1.x * b0.y + a1.y * b0.x;
+      t[3].x += a1.x * b1.x - a1.y * b1.y; t[3].y += a1.x * b1.y + a1.y * b1.x;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 v = cmul(u[(2 * i + j) * 4 + k], t[k]);
+          acc.x += v.x;
+          acc.y += v.y;
+        }
+        C[(size_t)(i * Dl + a) * m + j * Dr + r] = acc;
+      }
+  }
+  __syncthreads();
+
+  // ---- Eq. (C~): rows lambda_a C[(i,a)] into registers; ||C~||_F^2 in a fixed order
+  int nb = (n + FB - 1) / FB;
+  nb = nb < 2 ? 2 : nb + (nb & 1);
+  const int nwa = nb / 2;
+  double2 T[FB][E], B[FB][E];
+  double part = 0.0;
+  {
+    const int gt = wv * FB, gb = (nb - 1 - wv) * FB;
+#pragma unroll
+    for (int t = 0; t < FB; ++t)
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int e = lane + 64 * k;
+        double2 vt = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+        if (wv < nwa && e < m) {
+          const int rt = gt + t, rb = gb + t;
+          if (rt < n) {
+            const double l = g.lam_l[rt % Dl];
+            const double2 cv = C[(size_t)rt * m + e];
+            vt = make_double2(l * cv.x, l * cv.y);
+          }
+          if (rb < n) {
+            const double l = g.lam_l[rb % Dl];
+            const double2 cv = C[(size_t)rb * m + e];
+            vb = make_double2(l * cv.x, l * cv.y);
+          }
+        }
+        T[t][k] = vt;
+        B[t][k] = vb;
+        part += vt.x * vt.x + vt.y * vt.y + vb.x * vb.x + vb.y * vb.y;
+      }
+  }
+  part = wave_sum(part);
+  if (lane == 0) s_part[wv] = part;
+  if (threadIdx.x == 0) {
+    s_rot[0] = 0;
+    s_rot[1] = 0;
+  }
+  __syncthreads();
+  double fro2 = 0.0;
+#pragma unroll
+  for (int w = 0; w < FW; ++w) fro2 += s_part[w];
+  if (!isfinite(fro2)) {
+    if (threadIdx.x == 0) set_status(g, 1);
+    return;
+  }
+  const double eps = g.eps_scale * (double)m;
+  const double floor = eps * eps * fro2;
+
+  // ---- Algorithm 1
+  int done = 0;
+  for (int sw = 0; sw < g.max_sweeps; ++sw) {
+    int rot = 0;
+    for (int r = 0; r < nb - 1; ++r) {
+      if (wv < nwa) {
+        if (r == 0) rot += intra_all<E>(T, B, eps, floor, lane);
+        const bool top_is_i = pos_id(wv, r, nb) < pos_id(nb - 1 - wv, r, nb);
+        rot += cross_all<E>(T, B, top_is_i, eps, floor, lane);
+      }
+      if (nb > 2) advance<E>(T, B, xs, wv, nwa, lane);
+    }
+    if (lane == 0 && rot) atomicAdd(&s_rot[sw & 1], rot);
+    __syncthreads();
+    const int total = s_rot[sw & 1];
+    __syncthreads();
+    if (threadIdx.x == 0) s_rot[sw & 1] = 0;  // reused two sweeps on, after more barriers
+    if (total == 0) {
+      done = sw + 1;
+      break;
+    }
+  }
+  if (!done) {
+    if (threadIdx.x == 0) set_status(g, 2);
+    return;
+  }
+
+  // ---- sigma_i = ||row_i||, stable descending order, truncation
+  {
+    double nrm[2 * FB];
+#pragma unroll
+    for (int t = 0; t < FB; ++t) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        a += T[t][k].x * T[t][k].x + T[t][k].y * T[t][k].y;
+        b += B[t][k].x * B[t][k].x + B[t][k].y * B[t][k].y;
+      }
+      nrm[t] = a;
+      nrm[FB + t] = b;
+    }
+    wave_sum_n<2 * FB>(nrm);
+    if (wv < nwa && lane < 2 * FB) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2 * FB; ++t)
+        if (lane == t) v = nrm[t];
+      const int row = lane < FB ? wv * FB + lane : (nb - 1 - wv) * FB + (lane - FB);
+      if (row < n) s_sig[row] = sqrt(v);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += FW * 64) {
+    const double si = s_sig[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = s_sig[j];
+      rk += (sj > si) || (sj == si && j < i);
+    }
+    s_perm[rk] = i;
+    s_rank[i] = rk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    bool bad = false;
+    for (int a = 0; a < n; ++a) {
+      const double sv = s_sig[s_perm[a]];
+      if (!isfinite(sv)) bad = true;
+      tot += sv * sv;
+    }
+    const double nrm = sqrt(tot);
+    int k = 0;
+    while (k < n && s_sig[s_perm[k]] > g.cutoff * nrm) ++k;
+    const int capk = min(g.cap_k, min(n, m));
+    if (k < 1) k = 1;
+    if (k > capk) k = capk;
+    double kept2 = 0.0, disc2 = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double sv = s_sig[s_perm[a]];
+      if (a < k) kept2 += sv * sv;
+      else disc2 += sv * sv;
+    }
+    const double kept = sqrt(kept2);
+    s_ok = !(bad || !(kept > 0.0) || !isfinite(kept));
+    s_inv = s_ok ? 1.0 / kept : 0.0;
+    s_k = k;
+    if (s_ok) {
+      *g.disc += tot > 0.0 ? disc2 / tot : 0.0;
+      *g.sweeps += done;
+    } else {
+      set_status(g, 1);
+    }
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  const int k = s_k;
+  const double inv = s_inv;
+
+  // ---- Eq. (Bl): B_{q+1} <- V_k^+ as [j][p][r];  lambda_{q+1} <- sigma_k / ||sigma_k||
+  if (wv < nwa) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int base = h == 0 ? wv * FB : (nb - 1 - wv) * FB;
+#pragma unroll
+      for (int t = 0; t < FB; ++t) {
+        const int row = base + t;
+        if (row >= n) continue;
+        const int p = s_rank[row];
+        if (p >= k) continue;
+        const double sv = s_sig[row];
+        const double is = sv > 0.0 ? 1.0 / sv : 0.0;
+#pragma unroll
+        for (int kk = 0; kk < E; ++kk) {
+          const int e = lane + 64 * kk;
+          if (e < m) {
+            const double2 x = h == 0 ? T[t][kk] : B[t][kk];
+            const int j = e >= Dr ? 1 : 0, r = e - j * Dr;
+            g.bq1[((size_t)j * k + p) * Dr + r] = make_double2(x.x * is, x.y * is);
+          }
+        }
+      }
+    }
+  }
+  for (int p = threadIdx.x; p < k; p += FW * 64) g.lam_m[p] = s_sig[s_perm[p]] * inv;
+
+  // ---- Eq. (Bl): B_q[(i,a)][p] = inv sum_e C[(i,a)][e] conj(V^+[p][e]), 64 columns at a
+  // time, V^+ read back from the rows just stored in B_{q+1}
+  for (int p0 = 0; p0 < k; p0 += 64) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < m * 64; idx += FW * 64) {
+      const int e = idx >> 6, pp = idx & 63, p = p0 + pp;
+      double2 v = make_double2(0.0, 0.0);
+      if (p < k) {
+        const int j = e >= Dr ? 1 : 0, r = e - j * Dr;
+        const double2 x = g.bq1[((size_t)j * k + p) * Dr + r];
+        v = make_double2(x.x * inv, -x.y * inv);
+      }
+      xs[e * FVS + pp] = v;
+    }
+    __syncthreads();
+    // wave w: rows 16w .. 16w+15 of B_q; lane: column p0 + lane
+    const int r0 = wv * 16;
+    if (r0 < n) {
+      double2 acc[16];
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) acc[rr] = make_double2(0.0, 0.0);
+      for (int e = 0; e < m; ++e) {
+        const double2 v = xs[e * FVS + lane];
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+          const int row = min(r0 + rr, n - 1);
+          const double2 cv = C[(size_t)row * m + e];
+          acc[rr].x += cv.x * v.x - cv.y * v.y;
+          acc[rr].y += cv.x * v.y + cv.y * v.x;
+        }
+      }
+      const int p = p0 + lane;
+      if (p < k) {
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr)
+          if (r0 + rr < n) g.bq[(size_t)(r0 + rr) * k + p] = acc[rr];
+      }
+    }
+  }
+  if (threadIdx.x == 0) g.dims[g.q + 1] = k;
+}
+
+// Eq. (1q) with the bond dimensions read on the device.
+__global__ void gate1q_dev_kernel(double2* b, const double2* u, const int* dims, const int* status,
+                                  int q) {
+  if (status[0] != 0) return;
+  const int count = dims[q] * dims[q + 1];
+  const double2 u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const double2 x0 = b[i], x1 = b[count + i];
+    const double2 a = cmul(u00, x0), bb = cmul(u01, x1), c = cmul(u10, x0), d = cmul(u11, x1);
+    b[i] = make_double2(a.x + bb.x, a.y + bb.y);
+    b[count + i] = make_double2(c.x + d.x, c.y + d.y);
+  }
+}
+
+size_t fused_lds_bytes(int e) {
+  const size_t slots = (size_t)(FW) * FB * 64 * e * sizeof(double2);
+  const size_t vstage = (size_t)FMAXN * FVS * sizeof(double2);
+  return e == 1 ? std::max(slots, (size_t)64 * FVS * sizeof(double2)) : std::max(slots, vstage);
+}
+
+hipError_t configure_fused_lds() {
+  hipError_t e = hipFuncSetAttribute((const void*)gate2q_fused_kernel<1>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes(1));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)gate2q_fused_kernel<2>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes(2));
+}
+
+hipError_t launch_gate2q_fused(const FusedGate& g, int max_len, hipStream_t s) {
+  if (max_len <= 64) {
+    hipLaunchKernelGGL(gate2q_fused_kernel<1>, dim3(1), dim3(FW * 64), fused_lds_bytes(1), s, g);
+  } else if (max_len <= FMAXN) {
+    hipLaunchKernelGGL(gate2q_fused_kernel<2>, dim3(1), dim3(FW * 64), fused_lds_bytes(2), s, g);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gate1q_dev(double2* b, const double2* u, const int* dims, const int* status, int q,
+                             int max_count, hipStream_t s) {
+  const int blocks = std::max(1, std::min(64, (max_count + 255) / 256));
+  hipLaunchKernelGGL(gate1q_dev_kernel, dim3(blocks), dim3(256), 0, s, b, u, dims, status, q);
+  return hipGetLastError();
+}
+
+}  // namespace mps

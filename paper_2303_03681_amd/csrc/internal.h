@@ -111,7 +111,31 @@ struct GramTile {         // one 64x64 block of some bond's G that a string need
 // ---------------------------------------------------------------- launchers
 hipError_t launch_init_product(double2* const* sites, double* const* lam0, const uint8_t* bits,
                                int n, hipStream_t s);
+// One fused two-qubit gate (Eqs. C, C~, svd, Bl with Algorithm 1) on one
+// workgroup; bond dimensions live in `dims` on the device.  The site and
+// lambda buffers are updated in place only when the SVD converged.
+struct FusedGate {
+  double2* bq;          // site q:   [2][D_l][D_m] in, [2][D_l][k] out
+  double2* bq1;         // site q+1: [2][D_m][D_r] in, [2][k][D_r] out
+  const double* lam_l;  // lambda at bond q (D_l)
+  double* lam_m;        // lambda at bond q+1 (k out)
+  const double2* u;     // 4x4 gate, row-major, row index 2 i_q + i_{q+1}
+  int* dims;            // bond dimensions (n + 1), dims[q+1] <- k
+  double2* c;           // scratch, >= 2 D_l x 2 D_r
+  int* status;          // [0]: 0 ok, 1 non-finite, 2 no convergence; [1]: failing gate
+  double* disc;         // += relative discarded weight
+  int* sweeps;          // += sweeps used
+  int q, gate;          // bond index of D_l; gate index reported on failure
+  int cap_k;            // capacity of bond q+1
+  int max_sweeps;
+  double cutoff, eps_scale;
+};
+
 hipError_t launch_gate1q(double2* b, const double2* u, int count, hipStream_t s);
+hipError_t launch_gate1q_dev(double2* b, const double2* u, const int* dims, const int* status, int q,
+                             int max_count, hipStream_t s);
+hipError_t launch_gate2q_fused(const FusedGate& g, int max_len, hipStream_t s);
+hipError_t configure_fused_lds();
 hipError_t launch_theta(const ThetaItem* items_dev, int items, int max_rows, int max_cols,
                         hipStream_t s);
 hipError_t launch_mix(const MixItem* items_dev, int items, int max_dldr, hipStream_t s);

@@ -19,41 +19,11 @@
 
 #include "gemm_core.h"
 #include "internal.h"
+#include "wave_ops.h"
 
 namespace mps {
 
 namespace {
-
-// Sum over the 64 lanes of a wave, the same bits in every lane (each step
-// adds a and b in both orders, and a + b == b + a exactly): DPP moves within
-// rows of 16 lanes, then two cross-row exchanges.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// A wave-uniform value moved to scalar registers (it is identical in all lanes).
-__device__ __forceinline__ double wave_uniform(double x) {
-  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
-  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_mov<0x141>(v);  // row_half_mirror
-  v += dpp_mov<0x140>(v);  // row_mirror
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
 
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 

@@ -149,6 +149,14 @@ struct mps_state {
   double* d_scale = nullptr;
   double* d_disc = nullptr;
   int* d_status = nullptr;
+  // fused single-gate path: bond dimensions on the device while a run of
+  // fused gates is queued (host dims are stale until fused_flush)
+  bool fused_enabled = true;
+  bool fused_active = false;
+  int* d_dims = nullptr;
+  int* d_fstat = nullptr;   // [0] status, [1] failing gate (chunk-relative)
+  double* d_fdisc = nullptr;
+  int* d_fsweeps = nullptr;
   double2* d_carry[2] = {nullptr, nullptr};
   void* d_desc = nullptr;
   size_t desc_bytes = 0;
@@ -234,6 +242,7 @@ mps_status ensure_lds(mps_state* h) {
   b = b > 8 * 1024 ? b - 8 * 1024 : b;  // room for the kernels' static shared arrays
   if (b > 152 * 1024) b = 152 * 1024;
   HIP_TRY(h, configure_jacobi_lds(b));
+  HIP_TRY(h, configure_fused_lds());
   g_lds_budget = b;
   return MPS_OK;
 }
@@ -1034,6 +1043,69 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
+// ----------------------------------------------------------------------------
+// fused single-gate path (one workgroup per gate, ranks kept on the device)
+
+constexpr int kFusedMaxLen = 128;  // 2 D_l and 2 D_r limit of the fused kernel
+constexpr int kFusedMaxBatch = 4;  // larger disjoint batches use the batched path
+
+bool fused_eligible(const mps_state* h, int q) {
+  return 2 * h->cap[q] <= kFusedMaxLen && 2 * h->cap[q + 2] <= kFusedMaxLen;
+}
+
+mps_status fused_begin(mps_state* h) {
+  if (h->fused_active) return MPS_OK;
+  mps_status st = ensure_ws(h, 1);
+  if (st != MPS_OK) return st;
+  if ((st = upload(h, h->d_dims, h->dims.data(), sizeof(int) * (h->n + 1))) != MPS_OK) return st;
+  HIP_TRY(h, hipMemsetAsync(h->d_fstat, 0, 2 * sizeof(int), h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_fdisc, 0, sizeof(double), h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_fsweeps, 0, sizeof(int), h->stream));
+  h->fused_active = true;
+  return MPS_OK;
+}
+
+// Ends a run of fused gates: reads back ranks, status and accumulators.  On a
+// failed gate, *failed_at = its chunk-relative index and *code its status
+// (the gates before it were applied, it and the later ones were not).
+mps_status fused_flush(mps_state* h, int64_t* failed_at, int* code) {
+  *failed_at = -1;
+  *code = 0;
+  if (!h->fused_active) return MPS_OK;
+  std::vector<int> dims(h->n + 1);
+  int stat[2] = {0, 0}, sweeps = 0;
+  double disc = 0.0;
+  HIP_TRY(h, hipMemcpyAsync(dims.data(), h->d_dims, sizeof(int) * (h->n + 1), hipMemcpyDeviceToHost,
+                            h->stream));
+  HIP_TRY(h, hipMemcpyAsync(stat, h->d_fstat, sizeof(stat), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&disc, h->d_fdisc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&sweeps, h->d_fsweeps, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  mps_status st = sync(h);
+  if (st != MPS_OK) return st;
+  h->fused_active = false;
+  for (int b = 0; b <= h->n; ++b)
+    if (dims[b] < 1 || dims[b] > h->cap[b]) {
+      h->poisoned = true;
+      return fail(MPS_ERR_DEVICE, "fused gates: bond dimension out of range");
+    }
+  h->dims = dims;
+  h->discarded += disc;
+  h->tm.jacobi_sweeps += sweeps;
+  if (stat[0] != 0) {
+    *failed_at = stat[1];
+    *code = stat[0];
+  }
+  return MPS_OK;
+}
+
+mps_status fused_launch(mps_state* h, int q, const double2* u, int gate) {
+  FusedGate g{h->cur(q), h->cur(q + 1), h->lcur(q), h->lcur(q + 1), u, h->d_dims, h->ws_c,
+              h->d_fstat, h->d_fdisc, h->d_fsweeps, q, gate, h->cap[q + 1], h->max_sweeps,
+              h->cutoff, kEpsScale};
+  HIP_TRY(h, launch_gate2q_fused(g, 2 * h->cap[q + 2], h->stream));
+  return MPS_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -1103,6 +1175,10 @@ mps_status mps_create(const mps_config* cfg, mps_handle* out) {
   if ((st = dalloc_t(h.get(), &h->d_lam_ptrs, n + 1)) != MPS_OK) return st;
   if ((st = dalloc_t(h.get(), &h->d_bits, n)) != MPS_OK) return st;
   if ((st = dalloc_t(h.get(), &h->d_one, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_dims, n + 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_fstat, 2)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_fdisc, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_fsweeps, 1)) != MPS_OK) return st;
   const double one = 1.0;
   HIP_TRY(h.get(), hipMemcpy(h->d_one, &one, sizeof(double), hipMemcpyHostToDevice));
   if ((st = mps_reset(h.get(), cfg->init_bits)) != MPS_OK) return st;
@@ -1180,33 +1256,70 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
     HIP_TRY(h, hipMemcpy(h->d_gates, u + 32 * c0, sizeof(double) * 32 * (c1 - c0),
                          hipMemcpyHostToDevice));
     int64_t i = c0;
+    // ends a fused run; on a failed gate reports it and how many were applied
+    auto flush = [&]() -> mps_status {
+      int64_t bad = -1;
+      int code = 0;
+      mps_status s2 = fused_flush(h, &bad, &code);
+      if (s2 != MPS_OK) return s2;
+      if (bad >= 0) {
+        done = c0 + bad;
+        const std::string where = " (gate " + std::to_string(done) + " on qubit " +
+                                  std::to_string(q0[done]) + ")";
+        if (code == 2)
+          return fail(MPS_ERR_NOCONV, "Jacobi SVD did not converge within " +
+                                          std::to_string(h->max_sweeps) + " sweeps" + where);
+        return fail(MPS_ERR_NONFINITE, "non-finite or zero singular values" + where);
+      }
+      return MPS_OK;
+    };
+    auto finish = [&](mps_status s2) {
+      if (n_done) *n_done = done;
+      h->tm.gates_ms += now_ms() - t0;
+      return s2;
+    };
     while (i < c1) {
+      const double2* ug = h->d_gates + (size_t)(i - c0) * 16;
       if (q1[i] < 0) {
         const int q = q0[i];
-        HIP_TRY(h, launch_gate1q(h->cur(q), h->d_gates + (size_t)(i - c0) * 16,
-                                 h->dims[q] * h->dims[q + 1], h->stream));
+        if (h->fused_active)
+          HIP_TRY(h, launch_gate1q_dev(h->cur(q), ug, h->d_dims, h->d_fstat, q,
+                                       h->cap[q] * h->cap[q + 1], h->stream));
+        else
+          HIP_TRY(h, launch_gate1q(h->cur(q), ug, h->dims[q] * h->dims[q + 1], h->stream));
         h->canonical = false;
         ++i;
-        done = i;
+        if (!h->fused_active) done = i;
         continue;
       }
       std::vector<int> qs, gi;
       std::vector<char> used(h->n, 0);
       int64_t j = i;
+      bool all_small = true;
       while (j < c1 && q1[j] >= 0 && !used[q0[j]] && !used[q0[j] + 1] && (int)qs.size() < h->n) {
         used[q0[j]] = used[q0[j] + 1] = 1;
         qs.push_back(q0[j]);
         gi.push_back((int)(j - c0));
+        all_small = all_small && fused_eligible(h, q0[j]);
         ++j;
       }
-      if ((st = apply_2q_batch(h, qs, gi)) != MPS_OK) {
-        if (n_done) *n_done = done;
-        h->tm.gates_ms += now_ms() - t0;
-        return st;
+      if (h->fused_enabled && all_small && (int)qs.size() <= kFusedMaxBatch) {
+        if ((st = fused_begin(h)) != MPS_OK) return finish(st);
+        for (size_t b = 0; b < qs.size(); ++b)
+          if ((st = fused_launch(h, qs[b], h->d_gates + (size_t)gi[b] * 16, gi[b])) != MPS_OK)
+            return finish(st);
+        h->canonical = false;
+        i = j;
+        continue;
       }
+      if ((st = flush()) != MPS_OK) return finish(st);
+      done = i;
+      if ((st = apply_2q_batch(h, qs, gi)) != MPS_OK) return finish(st);
       i = j;
       done = i;
     }
+    if ((st = flush()) != MPS_OK) return finish(st);
+    done = c1;
   }
   if ((st = sync(h)) != MPS_OK) return st;
   if (n_done) *n_done = done;
@@ -1428,6 +1541,13 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
       }
   }
   if (sweeps) *sweeps = swp[0];
+  return MPS_OK;
+}
+
+mps_status mps_set_fused_gates(mps_handle h, int32_t enabled) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  h->fused_enabled = enabled != 0;
   return MPS_OK;
 }
 

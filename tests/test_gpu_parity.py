@@ -240,3 +240,109 @@ def test_canonicalize_idempotent(gpu_lib):
         B, _ = m.export_site(q)
         g = np.einsum("sab,scb->ac", B, B.conj())
         assert np.max(np.abs(g - np.eye(g.shape[0]))) < 1e-12
+
+
+def _random_u4(rng):
+    z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _ladder_gates(n, sweeps, seed):
+    """Random two-qubit unitaries swept up and down the chain: every gate
+    depends on the previous one (batches of one gate)."""
+    from workloads.circuits import Gate
+    rng = np.random.default_rng(seed)
+    gates = []
+    for s in range(sweeps):
+        bonds = range(n - 1) if s % 2 == 0 else range(n - 2, -1, -1)
+        gates += [Gate(q, q + 1, _random_u4(rng)) for q in bonds]
+    return gates
+
+
+@pytest.mark.parametrize("n,D,sweeps", [(9, 8, 4), (12, 32, 3), (14, 64, 3)])
+def test_fused_ladder_vs_oracle(gpu_lib, n, D, sweeps):
+    """Dependent gates take the fused one-workgroup path (rows of 2 D_l up to
+    128, both register widths); bond dimensions, discarded weight and every
+    string match the oracle, and the batched path gives the same state."""
+    from paper_2303_03681_amd import binding
+    _say(f"fused ladder n={n} D={D} sweeps={sweeps}")
+    gates = _ladder_gates(n, sweeps, 100 + n)
+    bits = hf_bits(n, n // 2)
+    o = MpsOracle(n, D, 1e-14, bits)
+    o.apply_gates(gates)
+    r = np.random.default_rng(n)
+    codes = r.integers(0, 4, size=(200, n)).astype(np.uint8)
+    coeffs = r.normal(size=200)
+    plan = binding.PauliSum(codes, coeffs)
+    results = []
+    for fused in (True, False):
+        m = binding.Mps(n, D, 1e-14, bits=bits)
+        m.set_fused_gates(fused)
+        _apply(m, gates)
+        assert list(m.bond_dims()) == o.bond_dims(), fused
+        assert abs(m.discarded_weight() - o.discarded) < 1e-10 * max(1.0, o.discarded)
+        e, per = m.expect(plan, "c128", per_term=True)
+        results.append((e, per))
+    o.canonicalize()
+    ref = o.expect_terms(codes).real
+    for e, per in results:
+        assert np.max(np.abs(per - ref)) < 1e-10
+        assert abs(e - math.fsum(coeffs * ref)) < 1e-9
+    assert abs(results[0][0] - results[1][0]) < 1e-10
+
+
+def test_fused_matches_batched_windowed_uccsd(gpu_lib):
+    """A 12-qubit windowed UCCSD circuit at D = 64 with cutoff 1e-10 (the
+    truncation rule of the 24-qubit workload; only the threshold cuts, the
+    discarded weight stays ~1e-20): fused and batched paths match the oracle.
+    (At D = 32 the same circuit cuts 1215 times with relative gaps down to
+    2e-10 at the cut, where different valid truncations drift apart; such
+    cases are not exact-parity cases.)"""
+    from paper_2303_03681_amd import binding
+    from workloads.circuits import uccsd_gates, uccsd_n_params
+    n, ne, D = 12, 6, 64
+    h, g = random_integrals(n // 2, workload_rng(4, 0, n))
+    ps = jw_hamiltonian(h, g)
+    th = workload_rng(4, 1, n).uniform(-0.1, 0.1, uccsd_n_params(n, ne, window=5))
+    gates = fuse_gates(uccsd_gates(n, ne, th, window=5), n)
+    _say(f"windowed uccsd n={n} gates={len(gates)}")
+    o = MpsOracle(n, D, 1e-10, hf_bits(n, ne))
+    o.apply_gates(gates)
+    o.canonicalize()
+    ref = o.expect_terms(ps.codes).real
+    e_ref = math.fsum(ps.coeffs * ref)
+    plan = binding.PauliSum(ps.codes, ps.coeffs)
+    for fused in (True, False):
+        m = binding.Mps(n, D, 1e-10, bits=hf_bits(n, ne))
+        m.set_fused_gates(fused)
+        _apply(m, gates)
+        assert list(m.bond_dims()) == o.bond_dims(), fused
+        e, per = m.expect(plan, "c128", per_term=True)
+        assert np.max(np.abs(per - ref)) < 1e-10, fused
+        assert abs(e - e_ref) < 1e-9, fused
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_noconv_reports_gates_applied(gpu_lib, fused):
+    """A sweep limit of 1 fails the first entangling gate that needs a second
+    sweep; the gates before it stay applied and nothing after it is."""
+    from paper_2303_03681_amd import binding
+    n = 8
+    ang = workload_rng(10, 1).uniform(-np.pi, np.pi, size=(3, n, 2))
+    gates = fuse_gates(brickwork_gates(n, ang), n)
+    q0, q1, u = pack_gates(gates)
+    m = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, 4), max_jacobi_sweeps=1)
+    m.set_fused_gates(fused)
+    with pytest.raises(binding.MpsError) as ex:
+        m.apply_gates(q0, q1, u)
+    assert ex.value.name == "MPS_ERR_NOCONV"
+    k = ex.value.n_done
+    assert 0 <= k < len(gates)
+    ref = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, 4))
+    ref.set_fused_gates(fused)
+    if k:
+        assert ref.apply_gates(q0[:k], q1[:k], u[:k]) == k
+    assert list(m.bond_dims()) == list(ref.bond_dims())
+    plan = binding.PauliSum(np.eye(n, dtype=np.uint8) * 3, np.ones(n))
+    assert abs(m.expect(plan) - ref.expect(plan)) < 1e-12
