@@ -92,6 +92,7 @@ _SIGS = {
     "mps_jacobi_svd": [_I32, _I32, _P, _P, _P, _P],
     "mps_set_timing": [_P, _I32],
     "mps_set_fused_gates": [_P, _I32],
+    "mps_apply_gates_multi": [_I32, _P, _P, _P, _P, _P, _P, _P],
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
     "mps_selftest_mfma": [_P],
@@ -302,6 +303,41 @@ class Mps:
             self.close()
         except Exception:
             pass
+
+
+def apply_gates_multi(mpss, gate_lists, stream=None) -> np.ndarray:
+    """Apply gate_lists[i] = (q0, q1, u_packed) to mpss[i] for every i in one
+    sequence of device launches (the gate chains advance together, one
+    workgroup per MPS).  Returns the number of gates applied per MPS; on a
+    failed gate raises MpsError with .n_done set to that array."""
+    n = len(mpss)
+    if n != len(gate_lists):
+        raise ValueError("one gate list per MPS")
+    keep = []
+    hs = (C.c_void_p * n)()
+    p0 = (C.c_void_p * n)()
+    p1 = (C.c_void_p * n)()
+    pu = (C.c_void_p * n)()
+    ng = np.zeros(n, np.int64)
+    for i, (m, (q0, q1, u)) in enumerate(zip(mpss, gate_lists)):
+        q0 = np.ascontiguousarray(q0, dtype=np.int32)
+        q1 = np.ascontiguousarray(q1, dtype=np.int32)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if q1.size != q0.size or u.size != 32 * q0.size:
+            raise ValueError("u_packed must hold 32 doubles per gate")
+        keep += [q0, q1, u]
+        hs[i] = m._h
+        p0[i], p1[i], pu[i] = _ptr(q0), _ptr(q1), _ptr(u)
+        ng[i] = q0.size
+    done = np.zeros(n, np.int64)
+    try:
+        _check(_lib.mps_apply_gates_multi(n, C.cast(hs, C.c_void_p), _ptr(ng), C.cast(p0, C.c_void_p),
+                                          C.cast(p1, C.c_void_p), C.cast(pu, C.c_void_p),
+                                          stream, _ptr(done)))
+    except MpsError as err:
+        err.n_done = done
+        raise
+    return done
 
 
 def jacobi_svd(vectors: np.ndarray):

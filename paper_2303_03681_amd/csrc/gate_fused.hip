@@ -325,17 +325,30 @@ __device__ __forceinline__ void set_status(const FusedGate& g, int code) {
 
 }  // namespace
 
+// Workgroup-shared scalars of one gate.
+struct FusedShared {
+  double sig[FMAXN];
+  int perm[FMAXN];
+  int rank[FMAXN];
+  double part[FW];
+  int rot[2];
+  int k;
+  double inv;
+  int ok;
+};
+
+// One two-qubit gate by the whole workgroup; xs is the dynamic LDS (block
+// slots, then the staged V^+).  Every thread returns at the same point.
 template <int E>
-__global__ __launch_bounds__(FW * 64) void gate2q_fused_kernel(FusedGate g) {
-  extern __shared__ double2 xs[];  // block slots, then the staged V^+
-  __shared__ double s_sig[FMAXN];
-  __shared__ int s_perm[FMAXN];
-  __shared__ int s_rank[FMAXN];
-  __shared__ double s_part[FW];
-  __shared__ int s_rot[2];
-  __shared__ int s_k;
-  __shared__ double s_inv;
-  __shared__ int s_ok;
+__device__ __forceinline__ void gate_body(const FusedGate& g, double2* xs, FusedShared& sh) {
+  double* s_sig = sh.sig;
+  int* s_perm = sh.perm;
+  int* s_rank = sh.rank;
+  double* s_part = sh.part;
+  int* s_rot = sh.rot;
+  int& s_k = sh.k;
+  double& s_inv = sh.inv;
+  int& s_ok = sh.ok;
 
   if (g.status[0] != 0) return;  // an earlier gate of this run failed: apply nothing
   const int Dl = g.dims[g.q], Dm = g.dims[g.q + 1], Dr = g.dims[g.q + 2];
@@ -595,6 +608,47 @@ __global__ __launch_bounds__(FW * 64) void gate2q_fused_kernel(FusedGate g) {
   if (threadIdx.x == 0) g.dims[g.q + 1] = k;
 }
 
+// Register width from the actual row length 2 D_r.
+__device__ __forceinline__ void gate_any(const FusedGate& g, double2* xs, FusedShared& sh) {
+  if (2 * g.dims[g.q + 2] <= 64) gate_body<1>(g, xs, sh);
+  else gate_body<2>(g, xs, sh);
+}
+
+__global__ __launch_bounds__(FW * 64) void gate2q_fused_kernel(FusedGate g) {
+  extern __shared__ double2 xs[];
+  __shared__ FusedShared sh;
+  gate_any(g, xs, sh);
+}
+
+// One step of several gate lists: workgroup f applies gate g0 + step of run
+// f (Eq. 1q in place, or a two-qubit gate by gate_any) unless its list is
+// exhausted or an earlier gate of the run failed.  The host enqueues the
+// steps in order on one stream.
+__global__ __launch_bounds__(FW * 64) void fused_step_kernel(const FusedRun* runs, int64_t step) {
+  extern __shared__ double2 xs[];
+  __shared__ FusedShared sh;
+  const FusedRun r = runs[blockIdx.x];
+  const int64_t gi = r.g0 + step;
+  if (gi >= r.g1 || r.status[0] != 0) return;
+  const int q = r.q0[gi];
+  const double2* u = r.u + (size_t)gi * 16;
+  if (r.q1[gi] < 0) {
+    double2* b = r.sites[q];
+    const int count = r.dims[q] * r.dims[q + 1];
+    const double2 u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+    for (int i = threadIdx.x; i < count; i += FW * 64) {
+      const double2 x0 = b[i], x1 = b[count + i];
+      const double2 a = cmul(u00, x0), bb = cmul(u01, x1), c = cmul(u10, x0), d = cmul(u11, x1);
+      b[i] = make_double2(a.x + bb.x, a.y + bb.y);
+      b[count + i] = make_double2(c.x + d.x, c.y + d.y);
+    }
+    return;
+  }
+  const FusedGate g{r.sites[q], r.sites[q + 1], r.lam[q], r.lam[q + 1], u, r.dims, r.c, r.status,
+                    r.disc, r.sweeps, q, (int)gi, r.cap[q + 1], r.max_sweeps, r.cutoff, r.eps_scale};
+  gate_any(g, xs, sh);
+}
+
 // Eq. (1q) with the bond dimensions read on the device.
 __global__ void gate1q_dev_kernel(double2* b, const double2* u, const int* dims, const int* status,
                                   int q) {
@@ -609,28 +663,30 @@ __global__ void gate1q_dev_kernel(double2* b, const double2* u, const int* dims,
   }
 }
 
-size_t fused_lds_bytes(int e) {
-  const size_t slots = (size_t)(FW) * FB * 64 * e * sizeof(double2);
+size_t fused_lds_bytes() {
+  const size_t slots = (size_t)FW * FB * 64 * 2 * sizeof(double2);
   const size_t vstage = (size_t)FMAXN * FVS * sizeof(double2);
-  return e == 1 ? std::max(slots, (size_t)64 * FVS * sizeof(double2)) : std::max(slots, vstage);
+  return std::max(slots, vstage);
 }
 
 hipError_t configure_fused_lds() {
-  hipError_t e = hipFuncSetAttribute((const void*)gate2q_fused_kernel<1>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes(1));
+  hipError_t e = hipFuncSetAttribute((const void*)gate2q_fused_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes());
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)gate2q_fused_kernel<2>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes(2));
+  return hipFuncSetAttribute((const void*)fused_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)fused_lds_bytes());
 }
 
 hipError_t launch_gate2q_fused(const FusedGate& g, int max_len, hipStream_t s) {
-  if (max_len <= 64) {
-    hipLaunchKernelGGL(gate2q_fused_kernel<1>, dim3(1), dim3(FW * 64), fused_lds_bytes(1), s, g);
-  } else if (max_len <= FMAXN) {
-    hipLaunchKernelGGL(gate2q_fused_kernel<2>, dim3(1), dim3(FW * 64), fused_lds_bytes(2), s, g);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  if (max_len > FMAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gate2q_fused_kernel, dim3(1), dim3(FW * 64), fused_lds_bytes(), s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_step(const FusedRun* runs_dev, int n_runs, int64_t step, hipStream_t s) {
+  if (n_runs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fused_step_kernel, dim3(n_runs), dim3(FW * 64), fused_lds_bytes(), s, runs_dev,
+                     step);
   return hipGetLastError();
 }
 

@@ -131,11 +131,31 @@ struct FusedGate {
   double cutoff, eps_scale;
 };
 
+// One MPS's gate list for fused_step_kernel (one workgroup per run).  Every
+// two-qubit gate must satisfy 2 cap[q] <= 128 and 2 cap[q+2] <= 128.
+struct FusedRun {
+  double2* const* sites;  // current site buffers (n)
+  double* const* lam;     // current lambda buffers (n + 1)
+  const int* cap;         // bond capacities (n + 1)
+  int* dims;
+  double2* c;             // scratch, >= 2 cap x 2 cap
+  int* status;
+  double* disc;
+  int* sweeps;
+  const int32_t* q0;      // gate list on the device
+  const int32_t* q1;
+  const double2* u;       // 16 complex per gate
+  int64_t g0, g1;         // gates applied: [g0, g1)
+  int max_sweeps;
+  double cutoff, eps_scale;
+};
+
 hipError_t launch_gate1q(double2* b, const double2* u, int count, hipStream_t s);
 hipError_t launch_gate1q_dev(double2* b, const double2* u, const int* dims, const int* status, int q,
                              int max_count, hipStream_t s);
 hipError_t launch_gate2q_fused(const FusedGate& g, int max_len, hipStream_t s);
 hipError_t configure_fused_lds();
+hipError_t launch_fused_step(const FusedRun* runs_dev, int n_runs, int64_t step, hipStream_t s);
 hipError_t launch_theta(const ThetaItem* items_dev, int items, int max_rows, int max_cols,
                         hipStream_t s);
 hipError_t launch_mix(const MixItem* items_dev, int items, int max_dldr, hipStream_t s);

@@ -157,6 +157,9 @@ struct mps_state {
   int* d_fstat = nullptr;   // [0] status, [1] failing gate (chunk-relative)
   double* d_fdisc = nullptr;
   int* d_fsweeps = nullptr;
+  int* d_cap = nullptr;       // bond capacities on the device (n + 1)
+  int32_t* d_gq = nullptr;    // gate qubits for the multi-MPS path: q0 then q1
+  size_t gq_cap = 0;
   double2* d_carry[2] = {nullptr, nullptr};
   void* d_desc = nullptr;
   size_t desc_bytes = 0;
@@ -1179,6 +1182,8 @@ mps_status mps_create(const mps_config* cfg, mps_handle* out) {
   if ((st = dalloc_t(h.get(), &h->d_fstat, 2)) != MPS_OK) return st;
   if ((st = dalloc_t(h.get(), &h->d_fdisc, 1)) != MPS_OK) return st;
   if ((st = dalloc_t(h.get(), &h->d_fsweeps, 1)) != MPS_OK) return st;
+  if ((st = dalloc_t(h.get(), &h->d_cap, n + 1)) != MPS_OK) return st;
+  HIP_TRY(h.get(), hipMemcpy(h->d_cap, h->cap.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
   const double one = 1.0;
   HIP_TRY(h.get(), hipMemcpy(h->d_one, &one, sizeof(double), hipMemcpyHostToDevice));
   if ((st = mps_reset(h.get(), cfg->init_bits)) != MPS_OK) return st;
@@ -1324,6 +1329,109 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
   if ((st = sync(h)) != MPS_OK) return st;
   if (n_done) *n_done = done;
   h->tm.gates_ms += now_ms() - t0;
+  return MPS_OK;
+}
+
+mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const int64_t* n_gates,
+                                 const int32_t* const* q0, const int32_t* const* q1,
+                                 const double* const* u, void* stream, int64_t* n_done) {
+  if (n_handles < 0) return fail(MPS_ERR_ARG, "n_handles < 0");
+  if (n_handles == 0) return MPS_OK;
+  if (!hs || !n_gates || !q0 || !q1 || !u) return fail(MPS_ERR_ARG, "NULL array");
+  if (n_handles > 65535) return fail(MPS_ERR_ARG, "at most 65535 handles per call");
+  for (int i = 0; i < n_handles; ++i) {
+    if (n_done) n_done[i] = 0;
+    mps_status st = check_handle(hs[i]);
+    if (st != MPS_OK) return st;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(MPS_ERR_ARG, "handles must be distinct");
+    mps_state* h = hs[i];
+    const int64_t ng = n_gates[i];
+    if (ng < 0 || (ng > 0 && (!q0[i] || !q1[i] || !u[i])))
+      return fail(MPS_ERR_ARG, "handle " + std::to_string(i) + ": bad gate arrays");
+    for (int64_t g = 0; g < ng; ++g) {
+      const int32_t a = q0[i][g], b = q1[i][g];
+      const std::string where = "handle " + std::to_string(i) + ", gate " + std::to_string(g);
+      if (a < 0 || a >= h->n) return fail(MPS_ERR_ARG, where + ": q0 out of range");
+      if (b >= 0 && (b != a + 1 || b >= h->n))
+        return fail(MPS_ERR_ARG, where + ": two-qubit gates must act on (q, q+1)");
+      if (b >= 0 && !fused_eligible(h, a))
+        return fail(MPS_ERR_ARG, where + ": bond capacity above the fused-gate limit (64)");
+      if (!finite_all(u[i] + 32 * g, b >= 0 ? 32 : 8))
+        return fail(MPS_ERR_NONFINITE, where + ": non-finite matrix entry");
+    }
+  }
+  const double t0 = now_ms();
+  hipStream_t s = stream ? (hipStream_t)stream : hs[0]->stream;
+  std::vector<FusedRun> runs(n_handles);
+  int64_t steps = 0;
+  for (int i = 0; i < n_handles; ++i) {
+    mps_state* h = hs[i];
+    const int64_t ng = n_gates[i];
+    steps = std::max(steps, ng);
+    mps_status st = ensure_ws(h, 1);
+    if (st != MPS_OK) return st;
+    if ((st = sync(h)) != MPS_OK) return st;
+    const size_t need = (size_t)std::max<int64_t>(ng, 1);
+    if (need * 16 > h->gates_cap) {
+      dfree(h, h->d_gates);
+      h->d_gates = nullptr;
+      h->gates_cap = 0;
+      if ((st = dalloc_t(h, &h->d_gates, need * 16)) != MPS_OK) return st;
+      h->gates_cap = need * 16;
+    }
+    if (need * 2 > h->gq_cap) {
+      dfree(h, h->d_gq);
+      h->d_gq = nullptr;
+      h->gq_cap = 0;
+      if ((st = dalloc_t(h, &h->d_gq, need * 2)) != MPS_OK) return st;
+      h->gq_cap = need * 2;
+    }
+    if (ng > 0) {
+      HIP_TRY(h, hipMemcpy(h->d_gates, u[i], sizeof(double) * 32 * ng, hipMemcpyHostToDevice));
+      HIP_TRY(h, hipMemcpy(h->d_gq, q0[i], sizeof(int32_t) * ng, hipMemcpyHostToDevice));
+      HIP_TRY(h, hipMemcpy(h->d_gq + ng, q1[i], sizeof(int32_t) * ng, hipMemcpyHostToDevice));
+    }
+    std::vector<double2*> sp(h->n);
+    std::vector<double*> lp(h->n + 1);
+    for (int q = 0; q < h->n; ++q) sp[q] = h->cur(q);
+    for (int b = 0; b <= h->n; ++b) lp[b] = h->lcur(b);
+    HIP_TRY(h, hipMemcpy(h->d_site_ptrs, sp.data(), sizeof(double2*) * h->n, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->d_lam_ptrs, lp.data(), sizeof(double*) * (h->n + 1), hipMemcpyHostToDevice));
+    if ((st = fused_begin(h)) != MPS_OK) return st;
+    if ((st = sync(h)) != MPS_OK) return st;
+    runs[i] = FusedRun{h->d_site_ptrs, h->d_lam_ptrs, h->d_cap, h->d_dims, h->ws_c, h->d_fstat,
+                       h->d_fdisc, h->d_fsweeps, h->d_gq, h->d_gq + ng, (const double2*)h->d_gates,
+                       0, ng, h->max_sweeps, h->cutoff, kEpsScale};
+  }
+  mps_state* h0 = hs[0];
+  mps_status st = ensure_desc(h0, sizeof(FusedRun) * n_handles);
+  if (st != MPS_OK) return st;
+  HIP_TRY(h0, hipMemcpy(h0->d_desc, runs.data(), sizeof(FusedRun) * n_handles, hipMemcpyHostToDevice));
+  for (int64_t k = 0; k < steps; ++k)
+    HIP_TRY(h0, launch_fused_step((const FusedRun*)h0->d_desc, n_handles, k, s));
+  HIP_TRY(h0, hipStreamSynchronize(s));
+  const double dt = now_ms() - t0;
+  mps_status first = MPS_OK;
+  std::string first_msg;
+  for (int i = 0; i < n_handles; ++i) {
+    mps_state* h = hs[i];
+    int64_t bad = -1;
+    int code = 0;
+    if ((st = fused_flush(h, &bad, &code)) != MPS_OK) return st;
+    const int64_t done = bad >= 0 ? bad : n_gates[i];
+    if (n_done) n_done[i] = done;
+    if (done > 0) h->canonical = false;
+    h->tm.gates_ms += dt;
+    if (bad >= 0 && first == MPS_OK) {
+      first = code == 2 ? MPS_ERR_NOCONV : MPS_ERR_NONFINITE;
+      first_msg = std::string(code == 2 ? "Jacobi SVD did not converge within " +
+                                              std::to_string(h->max_sweeps) + " sweeps"
+                                        : "non-finite or zero singular values") +
+                  " (handle " + std::to_string(i) + ", gate " + std::to_string(bad) + ")";
+    }
+  }
+  if (first != MPS_OK) return fail(first, first_msg);
   return MPS_OK;
 }
 

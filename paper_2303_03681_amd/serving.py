@@ -1,0 +1,397 @@
+"""Continuous-batching request loop for VQE energy requests on resident MPSs.
+
+A fragment is one small molecule-sized problem (qubits, bond dimension,
+Hamiltonian plan, a list of parameter updates each compiled to a gate list).
+A request asks for the energy of one fragment at one update; updates of one
+fragment are served in order (an update may start only after the previous
+one of the same fragment has finished).  Each fragment's MPS stays resident
+on the device between its updates, together with its cached environment
+setup, until memory is needed for another fragment.
+
+The loop (Server.run):
+  1. admit arrived requests while a slot is free and the fragment fits in the
+     device-memory budget (idle resident fragments are evicted, least recently
+     used first, to make room); an admitted request resets its MPS to the
+     Hartree-Fock product state;
+  2. advance every admitted request by one chunk of gates in one batched call
+     (mps_apply_gates_multi: one device launch per gate index, one workgroup
+     per request, so all dependent gate chains move together);
+  3. requests whose gates are done get their energy (canonicalise + Pauli-sum
+     expectation) on a worker thread, on the MPS's own stream, overlapping the
+     next gate chunk of the others;
+  4. finished requests free their slot; arrivals are admitted between chunks.
+
+Latency of a request is arrival -> energy available; the report gives p50 and
+p99 next to the throughput.  The energy of a request does not depend on what
+else is in flight: each request's arithmetic is the same sequence of kernels
+on its own data.
+
+The policy is separated from the device through a small backend interface so
+that scheduling can be tested on the CPU.
+"""
+
+from __future__ import annotations
+
+import concurrent.futures as cf
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Fragment:
+    fid: int
+    n_qubits: int
+    max_bond: int
+    cutoff: float
+    bits: np.ndarray
+    codes: np.ndarray                 # Pauli strings, n_terms x n_qubits
+    coeffs: np.ndarray
+    updates: list                     # per update: (q0, q1, u_packed)
+    est_bytes: int = 0                # device-memory estimate before first use
+
+    @property
+    def n_terms(self) -> int:
+        return int(self.coeffs.size)
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Fragment":
+        return cls(d["fid"], d["n_qubits"], d["max_bond"], d["cutoff"], d["bits"], d["codes"],
+                   d["coeffs"], d["updates"])
+
+    def batchable(self) -> bool:
+        """Every bond capacity <= 64: its gates can share the batched launches."""
+        return max(min(self.max_bond, 2 ** min(b, self.n_qubits - b))
+                   for b in range(self.n_qubits + 1)) <= 64
+
+
+@dataclass
+class Request:
+    rid: int
+    fid: int
+    update: int
+    arrival: float                    # seconds after the start of the run
+    admitted: float = math.nan
+    gates_done: float = math.nan
+    finish: float = math.nan
+    energy: float = math.nan
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+def estimate_bytes(n_qubits: int, max_bond: int, n_env_updates: int, prec_bytes: int = 8) -> int:
+    """Upper estimate of one fragment's device memory: two site and lambda
+    buffers, the gate workspaces, the environment pool and its scratch."""
+    caps = [min(max_bond, 2 ** min(b, n_qubits - b)) for b in range(n_qubits + 1)]
+    sites = sum(2 * 2 * caps[q] * caps[q + 1] * 16 for q in range(n_qubits))
+    dmax = max(caps)
+    ws = 2 * (2 * dmax) ** 2 * 16 + 2 * dmax * dmax * 16
+    pool = (n_env_updates + 2 * (n_qubits + 1)) * dmax * dmax * prec_bytes
+    prepared = 2 * sites
+    scratch = 64 * dmax * 2 * dmax * prec_bytes
+    return int(sites + ws + pool + prepared + scratch + (8 << 20))
+
+
+# --------------------------------------------------------------------------
+# backends
+
+
+class GpuBackend:
+    """The HIP library: one Mps handle per resident fragment, batched gate
+    chunks on one server stream, expectations on the handles' own streams."""
+
+    def __init__(self, prec: str = "c64", expect_workers: int = 8):
+        import torch
+
+        from . import binding
+        self.binding = binding
+        self.prec = prec
+        self.stream = torch.cuda.Stream()
+        self.pool = cf.ThreadPoolExecutor(max_workers=expect_workers)
+        self.plans: dict[int, object] = {}
+
+    def create(self, frag: Fragment):
+        if frag.fid not in self.plans:
+            self.plans[frag.fid] = self.binding.PauliSum(frag.codes, frag.coeffs)
+        return self.binding.Mps(frag.n_qubits, frag.max_bond, frag.cutoff, bits=frag.bits)
+
+    def plan_updates(self, frag: Fragment) -> int:
+        if frag.fid not in self.plans:
+            self.plans[frag.fid] = self.binding.PauliSum(frag.codes, frag.coeffs)
+        st = self.plans[frag.fid].stats()
+        return int(st["left_updates"] + st["right_updates"])
+
+    def reset(self, handle, frag: Fragment):
+        handle.reset(frag.bits)
+
+    def apply_chunk(self, items):
+        """items: list of (handle, q0, q1, u) slices; returns gates applied."""
+        return self.binding.apply_gates_multi([it[0] for it in items],
+                                              [(it[1], it[2], it[3]) for it in items],
+                                              stream=self.stream.cuda_stream)
+
+    def submit_expect(self, handle, frag: Fragment):
+        plan = self.plans[frag.fid]
+        return self.pool.submit(handle.expect, plan, self.prec)
+
+    def submit_whole(self, handle, frag: Fragment, update: int):
+        """Gates and energy of one request on a worker thread (fragments
+        above the batched-gate limit), on the handle's own stream."""
+        plan = self.plans[frag.fid]
+        q0, q1, u = frag.updates[update]
+
+        def job():
+            handle.apply_gates(q0, q1, u)
+            return handle.expect(plan, self.prec)
+        return self.pool.submit(job)
+
+    def device_bytes(self, handle) -> int:
+        return int(handle.device_bytes())
+
+    def destroy(self, handle):
+        handle.close()
+
+    def shutdown(self):
+        self.pool.shutdown(wait=True)
+
+
+# --------------------------------------------------------------------------
+# the request loop
+
+
+@dataclass
+class _Active:
+    req: Request
+    frag: Fragment
+    handle: object
+    cursor: int = 0
+
+
+@dataclass
+class ServeReport:
+    requests: list
+    span_s: float
+    completed: int
+    strings: int
+    max_active: int
+    mean_active: float
+    evictions: int
+    chunks: int
+
+    def summary(self) -> dict:
+        lat = np.array([r.latency for r in self.requests if not math.isnan(r.finish)]) * 1e3
+        out = {
+            "completed": self.completed,
+            "span_s": self.span_s,
+            "requests_per_s": self.completed / self.span_s if self.span_s > 0 else 0.0,
+            "strings_per_s": self.strings / self.span_s if self.span_s > 0 else 0.0,
+            "max_active": self.max_active,
+            "mean_active": self.mean_active,
+            "evictions": self.evictions,
+            "gate_chunks": self.chunks,
+        }
+        if lat.size:
+            out["latency_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                 "p99": float(np.percentile(lat, 99)),
+                                 "mean": float(lat.mean()), "max": float(lat.max())}
+        return out
+
+
+class Server:
+    def __init__(self, fragments: list[Fragment], backend, max_active: int = 64,
+                 hbm_budget: int | None = None, chunk: int = 256, clock=time.perf_counter,
+                 sleep=time.sleep):
+        self.frags = {f.fid: f for f in fragments}
+        self.backend = backend
+        self.max_active = max_active
+        self.budget = hbm_budget
+        self.chunk = chunk
+        self.clock = clock
+        self.sleep = sleep
+        self.resident: dict[int, object] = {}      # fid -> handle
+        self.resident_bytes: dict[int, int] = {}
+        self.last_used: dict[int, float] = {}
+        self.busy: set[int] = set()                # fragments with a request in flight
+        self.evictions = 0
+        self.chunks = 0
+
+    # memory accounting -------------------------------------------------
+    def _need(self, frag: Fragment) -> int:
+        if frag.fid in self.resident:
+            return 0
+        if not frag.est_bytes:
+            frag.est_bytes = estimate_bytes(frag.n_qubits, frag.max_bond,
+                                            self.backend.plan_updates(frag))
+        return frag.est_bytes
+
+    def _used(self) -> int:
+        return sum(self.resident_bytes.values())
+
+    def _make_room(self, need: int) -> bool:
+        if self.budget is None:
+            return True
+        while self._used() + need > self.budget:
+            idle = [f for f in self.resident if f not in self.busy]
+            if not idle:
+                return False
+            victim = min(idle, key=lambda f: self.last_used.get(f, 0.0))
+            self.backend.destroy(self.resident.pop(victim))
+            self.resident_bytes.pop(victim, None)
+            self.evictions += 1
+        return True
+
+    # the loop ----------------------------------------------------------
+    def run(self, requests: list[Request], timeout_s: float = 3600.0) -> ServeReport:
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        per_frag: dict[int, list[int]] = {}
+        for r in reqs:
+            if r.fid not in self.frags:
+                raise ValueError(f"request {r.rid}: unknown fragment {r.fid}")
+            if not 0 <= r.update < len(self.frags[r.fid].updates):
+                raise ValueError(f"request {r.rid}: fragment {r.fid} has no update {r.update}")
+            per_frag.setdefault(r.fid, []).append(r.update)
+        for fid, ups in per_frag.items():
+            if sorted(ups) != list(range(len(ups))):
+                raise ValueError(f"fragment {fid}: requested updates must be 0, 1, ... once each")
+        next_update = {fid: 0 for fid in self.frags}  # updates are served in order
+        waiting: list[Request] = []                    # arrived, not admitted
+        upcoming = list(reqs)
+        active: list[_Active] = []
+        expecting: dict[cf.Future, _Active] = {}
+        done: list[Request] = []
+        t0 = self.clock()
+        active_samples = []
+        max_seen = 0
+        strings = 0
+        while len(done) < len(reqs):
+            now = self.clock() - t0
+            if now > timeout_s:
+                raise TimeoutError("serving loop exceeded its time limit")
+            while upcoming and upcoming[0].arrival <= now:
+                waiting.append(upcoming.pop(0))
+            # 1. admission (arrival order; a request waits for its fragment's
+            #    previous update and for a slot and memory)
+            in_flight = len(active) + len(expecting)
+            idle_before = in_flight == 0
+            still = []
+            for r in waiting:
+                frag = self.frags[r.fid]
+                if (in_flight >= self.max_active or r.fid in self.busy
+                        or r.update != next_update[r.fid]):
+                    still.append(r)
+                    continue
+                need = self._need(frag)
+                if not self._make_room(need):
+                    still.append(r)
+                    continue
+                if r.fid not in self.resident:
+                    self.resident[r.fid] = self.backend.create(frag)
+                    self.resident_bytes[r.fid] = need
+                h = self.resident[r.fid]
+                self.backend.reset(h, frag)
+                r.admitted = self.clock() - t0
+                self.busy.add(r.fid)
+                if frag.batchable():
+                    active.append(_Active(r, frag, h))
+                else:
+                    expecting[self.backend.submit_whole(h, frag, r.update)] = _Active(r, frag, h)
+                in_flight += 1
+            # nothing was in flight and nothing could be admitted: no later
+            # completion can free memory, so the budget is too small
+            stuck = idle_before and in_flight == 0 and bool(waiting) and all(
+                r.update == next_update[r.fid] and r.fid not in self.busy for r in waiting[:1])
+            waiting = still
+            max_seen = max(max_seen, in_flight)
+            # 2. one gate chunk for every admitted request
+            if active:
+                items = []
+                for a in active:
+                    q0, q1, u = a.frag.updates[a.req.update]
+                    c1 = min(len(q0), a.cursor + self.chunk)
+                    items.append((a.handle, q0[a.cursor:c1], q1[a.cursor:c1], u[a.cursor:c1]))
+                active_samples.append(len(active) + len(expecting))
+                try:
+                    applied = self.backend.apply_chunk(items)
+                    failed = None
+                except Exception as err:  # a failed gate: only its request fails
+                    applied = getattr(err, "n_done", None)
+                    failed = err
+                    if applied is None:
+                        raise
+                self.chunks += 1
+                keep = []
+                for a, it, k in zip(active, items, applied):
+                    n_slice = len(it[1])
+                    if k < n_slice:  # this request's gate failed
+                        a.req.error = str(failed)
+                        a.req.finish = self.clock() - t0
+                        self._release(a, next_update)
+                        done.append(a.req)
+                        continue
+                    a.cursor += n_slice
+                    if a.cursor >= len(a.frag.updates[a.req.update][0]):
+                        a.req.gates_done = self.clock() - t0
+                        expecting[self.backend.submit_expect(a.handle, a.frag)] = a
+                    else:
+                        keep.append(a)
+                active = keep
+            # 3. finished energies
+            for fut in [f for f in expecting if f.done()]:
+                a = expecting.pop(fut)
+                try:
+                    a.req.energy = float(fut.result())
+                    strings += a.frag.n_terms
+                except Exception as err:
+                    a.req.error = str(err)
+                a.req.finish = self.clock() - t0
+                self.resident_bytes[a.req.fid] = max(self.resident_bytes.get(a.req.fid, 0),
+                                                     self.backend.device_bytes(a.handle))
+                self._release(a, next_update)
+                done.append(a.req)
+            # 4. idle: wait for the next arrival or a finishing energy
+            if not active:
+                if expecting:
+                    cf.wait(list(expecting), timeout=0.05, return_when=cf.FIRST_COMPLETED)
+                elif stuck:
+                    r = waiting[0]
+                    raise RuntimeError(f"request {r.rid} (fragment {r.fid}) cannot be admitted: "
+                                       f"needs {self._need(self.frags[r.fid])} bytes, "
+                                       f"budget {self.budget}")
+                elif upcoming:
+                    self.sleep(max(0.0, min(0.05, upcoming[0].arrival - (self.clock() - t0))))
+        span = max(r.finish for r in done) - min(r.arrival for r in done)
+        return ServeReport(done, span, sum(1 for r in done if r.error is None), strings, max_seen,
+                           float(np.mean(active_samples)) if active_samples else 0.0,
+                           self.evictions, self.chunks)
+
+    def _release(self, a: _Active, next_update):
+        self.busy.discard(a.req.fid)
+        next_update[a.req.fid] = a.req.update + 1
+        self.last_used[a.req.fid] = self.clock()
+
+    def close(self):
+        for h in self.resident.values():
+            self.backend.destroy(h)
+        self.resident.clear()
+        self.resident_bytes.clear()
+
+
+# --------------------------------------------------------------------------
+# workload: DMET-like fragments with windowed UCCSD circuits
+
+
+def poisson_arrivals(n: int, rate: float, rng: np.random.Generator) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate."""
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def make_requests(n_fragments: int, n_updates: int, rate: float, rng) -> list[Request]:
+    """Request r goes to fragment r mod n_fragments, update r // n_fragments."""
+    t = poisson_arrivals(n_fragments * n_updates, rate, rng)
+    return [Request(r, r % n_fragments, r // n_fragments, float(t[r]))
+            for r in range(n_fragments * n_updates)]

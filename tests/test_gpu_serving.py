@@ -1,0 +1,147 @@
+"""GPU: batched gate chains of several MPSs in shared launches
+(mps_apply_gates_multi) and the serving loop built on them.  Each result must
+be the same alone and in the mix; the batched path must match the
+single-MPS path and, without truncation at the cap, the FP64 oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import MpsOracle
+from workloads import build_serving_fragments, hf_bits, pack_gates
+from workloads.circuits import Gate
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _random_u4(rng):
+    z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _ladder(n, sweeps, seed):
+    rng = np.random.default_rng(seed)
+    gates = []
+    for s in range(sweeps):
+        bonds = range(n - 1) if s % 2 == 0 else range(n - 2, -1, -1)
+        for q in bonds:
+            gates.append(Gate(q, q + 1, _random_u4(rng)))
+            if q % 3 == 0:  # some one-qubit gates in between
+                a = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+                gates.append(Gate(q, -1, np.linalg.qr(a)[0]))
+    return gates
+
+
+def test_apply_gates_multi_matches_single(gpu_lib):
+    from paper_2303_03681_amd import binding
+    shapes = [(9, 8, 3), (12, 32, 2), (14, 64, 2), (6, 4, 5)]
+    lists, singles, multis, oracles = [], [], [], []
+    for i, (n, D, sw) in enumerate(shapes):
+        gates = _ladder(n, sw, 300 + i)
+        lists.append(pack_gates(gates))
+        bits = hf_bits(n, n // 2)
+        a = binding.Mps(n, D, 1e-14, bits=bits)
+        a.apply_gates(*lists[-1])
+        singles.append(a)
+        multis.append(binding.Mps(n, D, 1e-14, bits=bits))
+        o = MpsOracle(n, D, 1e-14, bits)
+        o.apply_gates(gates)
+        oracles.append(o)
+    _say("apply_gates_multi over 4 MPSs")
+    done = binding.apply_gates_multi(multis, lists)
+    assert list(done) == [len(l[0]) for l in lists]
+    r = np.random.default_rng(0)
+    for (n, D, _), a, b, o in zip(shapes, singles, multis, oracles):
+        assert list(b.bond_dims()) == list(a.bond_dims()) == o.bond_dims()
+        assert abs(b.discarded_weight() - a.discarded_weight()) < 1e-14
+        codes = r.integers(0, 4, size=(100, n)).astype(np.uint8)
+        coeffs = r.normal(size=100)
+        plan = binding.PauliSum(codes, coeffs)
+        ea, pa = a.expect(plan, "c128", per_term=True)
+        eb, pb = b.expect(plan, "c128", per_term=True)
+        assert np.max(np.abs(pa - pb)) < 1e-12
+        o.canonicalize()
+        ref = o.expect_terms(codes).real
+        assert np.max(np.abs(pb - ref)) < 1e-10
+
+
+def test_apply_gates_multi_rejects_large_bonds(gpu_lib):
+    from paper_2303_03681_amd import binding
+    m = binding.Mps(16, 128, 1e-14)
+    q0, q1, u = pack_gates([Gate(7, 8, np.eye(4, dtype=complex))])
+    with pytest.raises(binding.MpsError) as ex:
+        binding.apply_gates_multi([m], [(q0, q1, u)])
+    assert ex.value.name == "MPS_ERR_ARG"
+    assert list(m.bond_dims()) == [1] * 17
+
+
+def _serve(frags, reqs, **kw):
+    """Run the loop; returns the report and the resident bytes per fragment."""
+    from paper_2303_03681_amd.serving import GpuBackend, Server
+    be = GpuBackend(prec=kw.pop("prec", "c128"))
+    srv = Server(frags, be, **kw)
+    try:
+        rep = srv.run(reqs, timeout_s=300)
+        held = dict(srv.resident_bytes)
+    finally:
+        srv.close()
+        be.shutdown()
+    return rep, held
+
+
+def test_serving_alone_vs_mix_and_oracle(gpu_lib):
+    from paper_2303_03681_amd import binding
+    from paper_2303_03681_amd.serving import Fragment, Request, make_requests
+    raw = build_serving_fragments(5, 2, qubits=(8, 10), bonds=(16, 32), max_strings=400)
+    frags = [Fragment.from_dict(d) for d in raw]
+    reqs = make_requests(5, 2, rate=400.0, rng=np.random.default_rng(3))
+    _say("serving mix of 5 fragments x 2 updates")
+    mix, _ = _serve(frags, reqs, max_active=8, chunk=64)
+    assert mix.completed == len(reqs)
+    e_mix = {(r.fid, r.update): r.energy for r in mix.requests}
+    for fid, upd in [(0, 0), (3, 1)]:
+        alone, _ = _serve(frags, [Request(0, fid, 0, 0.0)] if upd == 0 else
+                          [Request(0, fid, 0, 0.0), Request(1, fid, 1, 0.0)], max_active=1, chunk=64)
+        got = {(r.fid, r.update): r.energy for r in alone.requests}
+        assert abs(got[(fid, upd)] - e_mix[(fid, upd)]) <= 1e-12
+    # the plain single-MPS API and the oracle, on a fragment whose bond cap
+    # never truncates (only the 1e-10 threshold cuts)
+    k = next(i for i, f in enumerate(frags) if f.max_bond >= 2 ** (f.n_qubits // 2))
+    f = frags[k]
+    q0, q1, u = f.updates[1]
+    m = binding.Mps(f.n_qubits, f.max_bond, f.cutoff, bits=f.bits)
+    m.apply_gates(q0, q1, u)
+    e_api = m.expect(binding.PauliSum(f.codes, f.coeffs), "c128")
+    assert abs(e_api - e_mix[(k, 1)]) < 1e-10
+    from workloads import workload_rng
+    from workloads.circuits import fuse_gates, uccsd_gates, uccsd_n_params
+    n, ne = f.n_qubits, f.n_qubits // 2
+    th = workload_rng(4, 1, k + 1).uniform(-0.1, 0.1, size=(2, uccsd_n_params(n, ne, window=5)))[1]
+    o = MpsOracle(n, f.max_bond, f.cutoff, f.bits)
+    o.apply_gates(fuse_gates(uccsd_gates(n, ne, th, window=5), n))
+    o.canonicalize()
+    e_ref = math.fsum(f.coeffs * o.expect_terms(f.codes).real)
+    assert abs(e_mix[(k, 1)] - e_ref) < 1e-9
+
+
+def test_serving_budget_evicts_and_keeps_results(gpu_lib):
+    from paper_2303_03681_amd.serving import Fragment, make_requests
+    raw = build_serving_fragments(4, 2, qubits=(10, 12), bonds=(32,), max_strings=300)
+    frags = [Fragment.from_dict(d) for d in raw]
+    reqs = make_requests(4, 2, rate=1000.0, rng=np.random.default_rng(4))
+    free, held = _serve(frags, reqs, max_active=8, chunk=128)
+    one = max(max(f.est_bytes for f in frags), max(held.values()))
+    frags2 = [Fragment.from_dict(d) for d in raw]
+    tight, _ = _serve(frags2, reqs, max_active=8, chunk=128, hbm_budget=int(2.5 * one))
+    assert tight.completed == free.completed == len(reqs)
+    assert tight.evictions > 0
+    a = {(r.fid, r.update): r.energy for r in free.requests}
+    b = {(r.fid, r.update): r.energy for r in tight.requests}
+    for k in a:
+        assert abs(a[k] - b[k]) <= 1e-12

@@ -9,7 +9,8 @@ the FP64 oracle and the HIP library consume what it produces.
 
 Random numbers come from ``numpy.random.default_rng([230303681, config,
 purpose])`` with purpose 0 = integrals, 1 = angles, 2 = string sample,
-3 = arrivals, so every workload is reproducible from its config index.
+3 = arrivals, 4 = fragment shapes of the serving mix, so every workload is
+reproducible from its config index.
 """
 
 from .rng import workload_rng
@@ -36,7 +37,7 @@ from .circuits import (
     fuse_gates,
     pack_gates,
 )
-from .configs import CONFIGS, build_config
+from .configs import CONFIGS, build_config, build_serving_fragments
 
 __all__ = [
     "workload_rng",
@@ -61,4 +62,5 @@ __all__ = [
     "pack_gates",
     "CONFIGS",
     "build_config",
+    "build_serving_fragments",
 ]

@@ -18,9 +18,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .circuits import Gate, brickwork_gates, fuse_gates, uccsd_gates, uccsd_n_params
+from .circuits import Gate, brickwork_gates, fuse_gates, pack_gates, uccsd_gates, uccsd_n_params
 from .hamiltonian import PauliSum, hf_bits, jw_hamiltonian, random_integrals, sample_terms
-from .rng import PURPOSE_ANGLES, PURPOSE_INTEGRALS, PURPOSE_SAMPLE, workload_rng
+from .rng import PURPOSE_ANGLES, PURPOSE_INTEGRALS, PURPOSE_MIX, PURPOSE_SAMPLE, workload_rng
 
 
 @dataclass
@@ -87,3 +87,29 @@ def build_config(index: int, fuse: bool = True, with_gates: bool = True,
         if fuse:
             gates = fuse_gates(gates, n_q)
     return Workload(spec, n_q, bits, gates, psum, h, g, full.n_terms)
+
+
+def build_serving_fragments(n_fragments: int, n_updates: int,
+                            qubits=(12, 16, 20, 24, 28, 32, 36, 40), bonds=(32, 64, 128),
+                            max_strings: int = 1 << 16, window: int = 5,
+                            cutoff: float = 1e-10) -> list[dict]:
+    """DMET-like fragments of the serving mix (config 4): qubit count and bond
+    dimension drawn uniformly from the given sets, N_e = n/2, each with its
+    own random integrals, its JW sum sampled to at most max_strings, and
+    n_updates pre-drawn angle vectors U(-0.1, 0.1) of the windowed UCCSD
+    ansatz, each compiled (fused, packed) to a gate list."""
+    mix = workload_rng(4, PURPOSE_MIX)
+    shapes = [(int(mix.choice(qubits)), int(mix.choice(bonds))) for _ in range(n_fragments)]
+    out = []
+    for fid, (n, D) in enumerate(shapes):
+        ne = n // 2
+        h, g = random_integrals(n // 2, workload_rng(4, PURPOSE_INTEGRALS, fid + 1))
+        full = jw_hamiltonian(h, g)
+        psum = sample_terms(full, max_strings, workload_rng(4, PURPOSE_SAMPLE, fid + 1))
+        npar = uccsd_n_params(n, ne, window=window)
+        thetas = workload_rng(4, PURPOSE_ANGLES, fid + 1).uniform(-0.1, 0.1, size=(n_updates, npar))
+        updates = [pack_gates(fuse_gates(uccsd_gates(n, ne, th, window=window), n)) for th in thetas]
+        out.append({"fid": fid, "n_qubits": n, "max_bond": D, "cutoff": cutoff,
+                    "bits": hf_bits(n, ne), "codes": psum.codes, "coeffs": psum.coeffs,
+                    "updates": updates, "full_terms": full.n_terms})
+    return out

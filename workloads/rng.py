@@ -8,6 +8,7 @@ PURPOSE_INTEGRALS = 0
 PURPOSE_ANGLES = 1
 PURPOSE_SAMPLE = 2
 PURPOSE_ARRIVALS = 3
+PURPOSE_MIX = 4  # fragment shapes of the serving mix
 
 
 def workload_rng(config: int, purpose: int, extra: int = 0) -> np.random.Generator:
