@@ -88,6 +88,42 @@ def cpu_baseline(w, n_strings_sample: int = 24, n_gates_sample: int = 2) -> dict
     }
 
 
+def serving_sample(n_fragments: int, prec: str) -> dict:
+    """A bounded sample of the serving mix: DMET-like fragments (windowed
+    UCCSD, own random-integral Hamiltonians) arriving as a Poisson stream at
+    200 requests/s, served by the continuous-batching loop; latency p50/p99
+    and throughput, plus one request re-run alone (its energy must match)."""
+    from paper_2303_03681_amd.serving import Fragment, GpuBackend, Request, Server, make_requests
+    from workloads import build_serving_fragments
+
+    t0 = time.perf_counter()
+    qubits, bonds = (12, 16, 20), (16, 32)
+    raw = build_serving_fragments(n_fragments, 1, qubits=qubits, bonds=bonds)
+    frags = [Fragment.from_dict(d) for d in raw]
+    log(f"serving sample: {n_fragments} fragments built in {time.perf_counter() - t0:.1f} s")
+    reqs = make_requests(n_fragments, 1, rate=200.0, rng=np.random.default_rng([230303681, 4, 3]))
+    be = GpuBackend(prec=prec)
+    srv = Server(frags, be, max_active=64, chunk=64, chunk_s=1.0,
+                 log=lambda m: log("  serving " + m))
+    rep = srv.run(reqs, timeout_s=600)
+    srv.close()
+    out = rep.summary()
+    # the largest fragment alone: same energy as in the mix
+    big = max(frags, key=lambda f: (f.n_qubits, f.max_bond))
+    srv = Server(frags, be, max_active=1, chunk=64, chunk_s=1.0)
+    alone = srv.run([Request(0, big.fid, 0, 0.0)], timeout_s=600).requests[0]
+    srv.close()
+    e_mix = next(r.energy for r in rep.requests if r.fid == big.fid)
+    out.update({
+        "workload": (f"{n_fragments} fragments, qubits in {list(qubits)}, D in {list(bonds)}, "
+                     "windowed UCCSD, cutoff 1e-10, Poisson arrivals 200/s, one update each"),
+        "gates_per_request_mean": float(np.mean([len(f.updates[0][0]) for f in frags])),
+        "alone_vs_mix": {"fragment": big.fid, "latency_alone_s": alone.latency,
+                         "abs_dE": abs(alone.energy - e_mix)},
+    })
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +132,8 @@ def main():
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layers", type=int, default=None, help="override (smaller) layer count")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix sample")
+    ap.add_argument("--serving-fragments", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus "
@@ -228,6 +266,8 @@ def main():
         "discarded_weight": disc,
         "roofline": roofline,
     }
+    if not args.no_serving:
+        out["serving"] = serving_sample(args.serving_fragments, args.prec)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(w)

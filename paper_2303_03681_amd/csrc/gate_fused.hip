@@ -317,6 +317,37 @@ __device__ __forceinline__ void advance(double2 (&T)[FB][E], double2 (&B)[FB][E]
   if (wv == 0) blk_load<E>(B, xs, lane);
 }
 
+// Algorithm 1 on the rows held in T and B (nb blocks, positions as set up by
+// the caller: wave w holds blocks w and nb-1-w): sweeps until one makes no
+// rotation.  Returns the sweeps used, or 0 if max_sweeps were not enough.
+// The block arrangement is the initial one again on return.  s_rot: two ints
+// of shared memory, zero on entry.  Every thread of the workgroup calls this.
+template <int E>
+__device__ __forceinline__ int jacobi_sweeps(double2 (&T)[FB][E], double2 (&B)[FB][E], double2* xs,
+                                             int* s_rot, int nb, int max_sweeps, double eps,
+                                             double floor) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nwa = nb / 2;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    int rot = 0;
+    for (int r = 0; r < nb - 1; ++r) {
+      if (wv < nwa) {
+        if (r == 0) rot += intra_all<E>(T, B, eps, floor, lane);
+        const bool top_is_i = pos_id(wv, r, nb) < pos_id(nb - 1 - wv, r, nb);
+        rot += cross_all<E>(T, B, top_is_i, eps, floor, lane);
+      }
+      if (nb > 2) advance<E>(T, B, xs, wv, nwa, lane);
+    }
+    if (lane == 0 && rot) atomicAdd(&s_rot[sw & 1], rot);
+    __syncthreads();
+    const int total = s_rot[sw & 1];
+    __syncthreads();
+    if (threadIdx.x == 0) s_rot[sw & 1] = 0;  // reused two sweeps on, after more barriers
+    if (total == 0) return sw + 1;
+  }
+  return 0;
+}
+
 __device__ __forceinline__ void set_status(const FusedGate& g, int code) {
   g.status[1] = g.gate;
   __threadfence();
@@ -441,27 +472,7 @@ __device__ __forceinline__ void gate_body(const FusedGate& g, double2* xs, Fused
   const double floor = eps * eps * fro2;
 
   // ---- Algorithm 1
-  int done = 0;
-  for (int sw = 0; sw < g.max_sweeps; ++sw) {
-    int rot = 0;
-    for (int r = 0; r < nb - 1; ++r) {
-      if (wv < nwa) {
-        if (r == 0) rot += intra_all<E>(T, B, eps, floor, lane);
-        const bool top_is_i = pos_id(wv, r, nb) < pos_id(nb - 1 - wv, r, nb);
-        rot += cross_all<E>(T, B, top_is_i, eps, floor, lane);
-      }
-      if (nb > 2) advance<E>(T, B, xs, wv, nwa, lane);
-    }
-    if (lane == 0 && rot) atomicAdd(&s_rot[sw & 1], rot);
-    __syncthreads();
-    const int total = s_rot[sw & 1];
-    __syncthreads();
-    if (threadIdx.x == 0) s_rot[sw & 1] = 0;  // reused two sweeps on, after more barriers
-    if (total == 0) {
-      done = sw + 1;
-      break;
-    }
-  }
+  const int done = jacobi_sweeps<E>(T, B, xs, s_rot, nb, g.max_sweeps, eps, floor);
   if (!done) {
     if (threadIdx.x == 0) set_status(g, 2);
     return;
@@ -663,6 +674,61 @@ __global__ void gate1q_dev_kernel(double2* b, const double2* u, const int* dims,
   }
 }
 
+// Algorithm 1 alone on matrices of at most 128 rows of at most 128 complex
+// elements (one workgroup per item, all sweeps in one launch): rows it.w
+// (n x m, row-major) are rotated in place; *it.sweeps_done receives the
+// sweeps used, or -max_sweeps if they were not enough; ||w||_F^2 is read
+// from *it.fro2.
+template <int E>
+__device__ __forceinline__ void jacobi_small_body(const JacItem& it, int max_sweeps, double eps_scale,
+                                                  double2* xs, int* s_rot) {
+  const int n = it.n, m = it.m;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int nb = (n + FB - 1) / FB;
+  nb = nb < 2 ? 2 : nb + (nb & 1);
+  const int nwa = nb / 2;
+  double2 T[FB][E], B[FB][E];
+#pragma unroll
+  for (int t = 0; t < FB; ++t)
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = lane + 64 * k, rt = wv * FB + t, rb = (nb - 1 - wv) * FB + t;
+      const bool ok = wv < nwa && e < m;
+      T[t][k] = ok && rt < n ? it.w[(size_t)rt * m + e] : make_double2(0.0, 0.0);
+      B[t][k] = ok && rb < n ? it.w[(size_t)rb * m + e] : make_double2(0.0, 0.0);
+    }
+  const double eps = eps_scale * (double)m;
+  const double floor = eps * eps * (*it.fro2);
+  const int done = jacobi_sweeps<E>(T, B, xs, s_rot, nb, max_sweeps, eps, floor);
+  if (wv < nwa) {
+#pragma unroll
+    for (int t = 0; t < FB; ++t)
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int e = lane + 64 * k, rt = wv * FB + t, rb = (nb - 1 - wv) * FB + t;
+        if (e < m) {
+          if (rt < n) it.w[(size_t)rt * m + e] = T[t][k];
+          if (rb < n) it.w[(size_t)rb * m + e] = B[t][k];
+        }
+      }
+  }
+  if (threadIdx.x == 0) *it.sweeps_done = done > 0 ? done : -max_sweeps;
+}
+
+__global__ __launch_bounds__(FW * 64) void jacobi_small_kernel(const JacItem* items, int max_sweeps,
+                                                               double eps_scale) {
+  extern __shared__ double2 xs[];
+  __shared__ int s_rot[2];
+  const JacItem it = items[blockIdx.x];
+  if (threadIdx.x == 0) {
+    s_rot[0] = 0;
+    s_rot[1] = 0;
+  }
+  __syncthreads();
+  if (it.m <= 64) jacobi_small_body<1>(it, max_sweeps, eps_scale, xs, s_rot);
+  else jacobi_small_body<2>(it, max_sweeps, eps_scale, xs, s_rot);
+}
+
 size_t fused_lds_bytes() {
   const size_t slots = (size_t)FW * FB * 64 * 2 * sizeof(double2);
   const size_t vstage = (size_t)FMAXN * FVS * sizeof(double2);
@@ -673,8 +739,11 @@ hipError_t configure_fused_lds() {
   hipError_t e = hipFuncSetAttribute((const void*)gate2q_fused_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes());
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)fused_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)fused_lds_bytes());
+  e = hipFuncSetAttribute((const void*)fused_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)fused_lds_bytes());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)jacobi_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(FW * FB * 64 * 2 * sizeof(double2)));
 }
 
 hipError_t launch_gate2q_fused(const FusedGate& g, int max_len, hipStream_t s) {
@@ -687,6 +756,14 @@ hipError_t launch_fused_step(const FusedRun* runs_dev, int n_runs, int64_t step,
   if (n_runs <= 0) return hipSuccess;
   hipLaunchKernelGGL(fused_step_kernel, dim3(n_runs), dim3(FW * 64), fused_lds_bytes(), s, runs_dev,
                      step);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_small(const JacItem* items_dev, int items, int max_sweeps, double eps_scale,
+                               hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_small_kernel, dim3(items), dim3(FW * 64), FW * FB * 64 * 2 * sizeof(double2),
+                     s, items_dev, max_sweeps, eps_scale);
   return hipGetLastError();
 }
 

@@ -155,6 +155,8 @@ hipError_t launch_gate1q_dev(double2* b, const double2* u, const int* dims, cons
                              int max_count, hipStream_t s);
 hipError_t launch_gate2q_fused(const FusedGate& g, int max_len, hipStream_t s);
 hipError_t configure_fused_lds();
+hipError_t launch_jacobi_small(const JacItem* items_dev, int items, int max_sweeps, double eps_scale,
+                               hipStream_t s);
 hipError_t launch_fused_step(const FusedRun* runs_dev, int n_runs, int64_t step, hipStream_t s);
 hipError_t launch_theta(const ThetaItem* items_dev, int items, int max_rows, int max_cols,
                         hipStream_t s);

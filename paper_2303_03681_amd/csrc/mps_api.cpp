@@ -315,6 +315,7 @@ mps_status ensure_ws(mps_state* h, int items) {
 // batched one-sided Jacobi over items already described in host vectors
 
 struct JacobiPlanHost {
+  std::vector<JacItem> small;               // register single-launch (n, m <= 128)
   std::vector<JacItem> single, reg, block;  // LDS single-launch, register blocks, LDS blocks
   size_t single_lds = 0, block_lds = 0;
   int reg_pairs = 0, reg_rounds = 0, reg_max_m = 0;
@@ -323,10 +324,15 @@ struct JacobiPlanHost {
 
 constexpr int kRegBlock = 8;     // vectors per block of the register kernels (one per wave)
 constexpr int kRegMaxLen = 512;  // longest vector the register kernels hold
+constexpr int kSmallMax = 128;   // rows and row length of the one-workgroup register kernel
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
   for (JacItem it : all) {
+    if (it.n <= kSmallMax && it.m <= kSmallMax) {
+      jp.small.push_back(it);
+      continue;
+    }
     const size_t per_vec = (size_t)it.m * sizeof(double2);
     const int nloc = (it.n + 1) & ~1;
     if (nloc <= 1024 && (size_t)it.n * per_vec <= budget &&
@@ -372,17 +378,22 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
       return fail(MPS_ERR_STATE, "internal: Jacobi rotation counters not laid out [sweep][item]");
   JacobiPlanHost jp;
   plan_jacobi(all, jp);
-  const size_t bytes = (jp.single.size() + jp.reg.size() + jp.block.size()) * sizeof(JacItem);
+  const size_t bytes =
+      (jp.small.size() + jp.single.size() + jp.reg.size() + jp.block.size()) * sizeof(JacItem);
   mps_status st = ensure_desc(h, desc_off + bytes);
   if (st != MPS_OK) return st;
   char* base = (char*)h->d_desc + desc_off;
-  JacItem* d_single = (JacItem*)base;
+  JacItem* d_small = (JacItem*)base;
+  JacItem* d_single = d_small + jp.small.size();
   JacItem* d_reg = d_single + jp.single.size();
   JacItem* d_block = d_reg + jp.reg.size();
-  std::vector<JacItem> packed(jp.single);
+  std::vector<JacItem> packed(jp.small);
+  packed.insert(packed.end(), jp.single.begin(), jp.single.end());
   packed.insert(packed.end(), jp.reg.begin(), jp.reg.end());
   packed.insert(packed.end(), jp.block.begin(), jp.block.end());
   if ((st = upload(h, base, packed.data(), bytes)) != MPS_OK) return st;
+  if (!jp.small.empty())
+    HIP_TRY(h, launch_jacobi_small(d_small, (int)jp.small.size(), h->max_sweeps, kEpsScale, h->stream));
   if (!jp.single.empty())
     HIP_TRY(h, launch_jacobi_single(d_single, (int)jp.single.size(), h->max_sweeps, kEpsScale,
                                     jp.single_lds, h->stream));
@@ -427,17 +438,20 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
             break;
           }
   }
-  std::vector<int> single_sweeps(jp.single.size());
-  for (size_t j = 0; j < jp.single.size(); ++j)
-    HIP_TRY(h, hipMemcpyAsync(&single_sweeps[j], jp.single[j].sweeps_done, sizeof(int),
+  // one-launch items report their sweeps themselves
+  std::vector<JacItem> one(jp.small);
+  one.insert(one.end(), jp.single.begin(), jp.single.end());
+  std::vector<int> one_sweeps(one.size());
+  for (size_t j = 0; j < one.size(); ++j)
+    HIP_TRY(h, hipMemcpyAsync(&one_sweeps[j], one[j].sweeps_done, sizeof(int),
                               hipMemcpyDeviceToHost, h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
   sweeps_out.assign(count, -1);
   for (int i = 0; i < count; ++i)
     if (is_multi[i]) sweeps_out[i] = first_zero[i];
-  for (size_t j = 0; j < jp.single.size(); ++j) {
-    const int i = (int)(jp.single[j].rot - all[0].rot);
-    sweeps_out[i] = single_sweeps[j] > 0 ? single_sweeps[j] : -1;
+  for (size_t j = 0; j < one.size(); ++j) {
+    const int i = (int)(one[j].rot - all[0].rot);
+    sweeps_out[i] = one_sweeps[j] > 0 ? one_sweeps[j] : -1;
   }
   for (int v : sweeps_out)
     if (v > 0) h->tm.jacobi_sweeps += v;

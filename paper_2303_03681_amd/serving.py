@@ -17,9 +17,16 @@ The loop (Server.run):
      (mps_apply_gates_multi: one device launch per gate index, one workgroup
      per request, so all dependent gate chains move together);
   3. requests whose gates are done get their energy (canonicalise + Pauli-sum
-     expectation) on a worker thread, on the MPS's own stream, overlapping the
-     next gate chunk of the others;
+     expectation) between chunks;
   4. finished requests free their slot; arrivals are admitted between chunks.
+
+Energies run between gate chunks rather than beside them: the expectation
+and canonicalisation paths synchronise with the host many times, and streams
+beyond the device's few hardware queues share a queue in submission order, so
+each of those waits could otherwise stall behind a whole gate chunk.  Chunks
+are sized to a target duration so that arrivals wait at most about that long
+to join.  Fragments above the batched-gate limit (bond capacity > 64) are
+served whole (gates, then energy) between chunks.
 
 Latency of a request is arrival -> energy available; the report gives p50 and
 p99 next to the throughput.  The energy of a request does not depend on what
@@ -32,7 +39,6 @@ that scheduling can be tested on the CPU.
 
 from __future__ import annotations
 
-import concurrent.futures as cf
 import math
 import time
 from dataclasses import dataclass
@@ -102,28 +108,29 @@ def estimate_bytes(n_qubits: int, max_bond: int, n_env_updates: int, prec_bytes:
 
 
 class GpuBackend:
-    """The HIP library: one Mps handle per resident fragment, batched gate
-    chunks on one server stream, expectations on the handles' own streams."""
+    """The HIP library: one Mps handle per resident fragment; batched gate
+    chunks on one server stream; energies on the handles' own streams."""
 
-    def __init__(self, prec: str = "c64", expect_workers: int = 8):
+    def __init__(self, prec: str = "c64"):
         import torch
 
         from . import binding
         self.binding = binding
         self.prec = prec
         self.stream = torch.cuda.Stream()
-        self.pool = cf.ThreadPoolExecutor(max_workers=expect_workers)
         self.plans: dict[int, object] = {}
 
-    def create(self, frag: Fragment):
+    def _plan(self, frag: Fragment):
         if frag.fid not in self.plans:
             self.plans[frag.fid] = self.binding.PauliSum(frag.codes, frag.coeffs)
+        return self.plans[frag.fid]
+
+    def create(self, frag: Fragment):
+        self._plan(frag)
         return self.binding.Mps(frag.n_qubits, frag.max_bond, frag.cutoff, bits=frag.bits)
 
     def plan_updates(self, frag: Fragment) -> int:
-        if frag.fid not in self.plans:
-            self.plans[frag.fid] = self.binding.PauliSum(frag.codes, frag.coeffs)
-        st = self.plans[frag.fid].stats()
+        st = self._plan(frag).stats()
         return int(st["left_updates"] + st["right_updates"])
 
     def reset(self, handle, frag: Fragment):
@@ -135,20 +142,12 @@ class GpuBackend:
                                               [(it[1], it[2], it[3]) for it in items],
                                               stream=self.stream.cuda_stream)
 
-    def submit_expect(self, handle, frag: Fragment):
-        plan = self.plans[frag.fid]
-        return self.pool.submit(handle.expect, plan, self.prec)
+    def expect(self, handle, frag: Fragment) -> float:
+        return handle.expect(self._plan(frag), self.prec)
 
-    def submit_whole(self, handle, frag: Fragment, update: int):
-        """Gates and energy of one request on a worker thread (fragments
-        above the batched-gate limit), on the handle's own stream."""
-        plan = self.plans[frag.fid]
+    def apply_all(self, handle, frag: Fragment, update: int):
         q0, q1, u = frag.updates[update]
-
-        def job():
-            handle.apply_gates(q0, q1, u)
-            return handle.expect(plan, self.prec)
-        return self.pool.submit(job)
+        handle.apply_gates(q0, q1, u)
 
     def device_bytes(self, handle) -> int:
         return int(handle.device_bytes())
@@ -157,7 +156,7 @@ class GpuBackend:
         handle.close()
 
     def shutdown(self):
-        self.pool.shutdown(wait=True)
+        pass
 
 
 # --------------------------------------------------------------------------
@@ -204,13 +203,16 @@ class ServeReport:
 
 class Server:
     def __init__(self, fragments: list[Fragment], backend, max_active: int = 64,
-                 hbm_budget: int | None = None, chunk: int = 256, clock=time.perf_counter,
-                 sleep=time.sleep):
+                 hbm_budget: int | None = None, chunk: int = 256, chunk_s: float = 0.5,
+                 max_chunk: int = 4096, clock=time.perf_counter, sleep=time.sleep, log=None):
         self.frags = {f.fid: f for f in fragments}
         self.backend = backend
         self.max_active = max_active
         self.budget = hbm_budget
         self.chunk = chunk
+        self.chunk_s = chunk_s
+        self.max_chunk = max_chunk
+        self.log = log
         self.clock = clock
         self.sleep = sleep
         self.resident: dict[int, object] = {}      # fid -> handle
@@ -261,13 +263,29 @@ class Server:
         next_update = {fid: 0 for fid in self.frags}  # updates are served in order
         waiting: list[Request] = []                    # arrived, not admitted
         upcoming = list(reqs)
-        active: list[_Active] = []
-        expecting: dict[cf.Future, _Active] = {}
+        active: list[_Active] = []                     # gate chains in progress
+        ready: list[_Active] = []                      # gates done, energy pending
+        whole: list[_Active] = []                      # served whole (above the batched limit)
         done: list[Request] = []
         t0 = self.clock()
         active_samples = []
         max_seen = 0
         strings = 0
+        steps = self.chunk
+
+        def finish(a: _Active, energy=None, error=None):
+            nonlocal strings
+            if error is None:
+                a.req.energy = float(energy)
+                strings += a.frag.n_terms
+            else:
+                a.req.error = error
+            a.req.finish = self.clock() - t0
+            self.resident_bytes[a.req.fid] = max(self.resident_bytes.get(a.req.fid, 0),
+                                                 self.backend.device_bytes(a.handle))
+            self._release(a, next_update)
+            done.append(a.req)
+
         while len(done) < len(reqs):
             now = self.clock() - t0
             if now > timeout_s:
@@ -276,7 +294,7 @@ class Server:
                 waiting.append(upcoming.pop(0))
             # 1. admission (arrival order; a request waits for its fragment's
             #    previous update and for a slot and memory)
-            in_flight = len(active) + len(expecting)
+            in_flight = len(active) + len(ready) + len(whole)
             idle_before = in_flight == 0
             still = []
             for r in waiting:
@@ -296,10 +314,7 @@ class Server:
                 self.backend.reset(h, frag)
                 r.admitted = self.clock() - t0
                 self.busy.add(r.fid)
-                if frag.batchable():
-                    active.append(_Active(r, frag, h))
-                else:
-                    expecting[self.backend.submit_whole(h, frag, r.update)] = _Active(r, frag, h)
+                (active if frag.batchable() else whole).append(_Active(r, frag, h))
                 in_flight += 1
             # nothing was in flight and nothing could be admitted: no later
             # completion can free memory, so the budget is too small
@@ -307,62 +322,67 @@ class Server:
                 r.update == next_update[r.fid] and r.fid not in self.busy for r in waiting[:1])
             waiting = still
             max_seen = max(max_seen, in_flight)
-            # 2. one gate chunk for every admitted request
+            # 2. energies of requests whose gates are done; whole requests
+            for a in ready:
+                try:
+                    finish(a, self.backend.expect(a.handle, a.frag))
+                except Exception as err:
+                    finish(a, error=str(err))
+            ready = []
+            for a in whole:
+                try:
+                    self.backend.apply_all(a.handle, a.frag, a.req.update)
+                    a.req.gates_done = self.clock() - t0
+                    finish(a, self.backend.expect(a.handle, a.frag))
+                except Exception as err:
+                    finish(a, error=str(err))
+            whole = []
+            # 3. one gate chunk for every admitted request
             if active:
                 items = []
                 for a in active:
                     q0, q1, u = a.frag.updates[a.req.update]
-                    c1 = min(len(q0), a.cursor + self.chunk)
+                    c1 = min(len(q0), a.cursor + steps)
                     items.append((a.handle, q0[a.cursor:c1], q1[a.cursor:c1], u[a.cursor:c1]))
-                active_samples.append(len(active) + len(expecting))
+                active_samples.append(len(active))
+                tc = self.clock()
+                failed = None
                 try:
                     applied = self.backend.apply_chunk(items)
-                    failed = None
                 except Exception as err:  # a failed gate: only its request fails
                     applied = getattr(err, "n_done", None)
                     failed = err
                     if applied is None:
                         raise
+                dt = self.clock() - tc
                 self.chunks += 1
+                longest = max(len(it[1]) for it in items)
+                if longest > 0 and dt > 0:  # size the next chunk to the target duration
+                    steps = int(min(self.max_chunk, max(16, self.chunk_s * longest / dt)))
                 keep = []
                 for a, it, k in zip(active, items, applied):
                     n_slice = len(it[1])
                     if k < n_slice:  # this request's gate failed
-                        a.req.error = str(failed)
-                        a.req.finish = self.clock() - t0
-                        self._release(a, next_update)
-                        done.append(a.req)
+                        finish(a, error=str(failed))
                         continue
                     a.cursor += n_slice
                     if a.cursor >= len(a.frag.updates[a.req.update][0]):
                         a.req.gates_done = self.clock() - t0
-                        expecting[self.backend.submit_expect(a.handle, a.frag)] = a
+                        ready.append(a)
                     else:
                         keep.append(a)
+                if self.log:
+                    self.log(f"chunk {self.chunks}: {len(items)} chains x {longest} gates in "
+                             f"{dt:.2f} s; {len(done)}/{len(reqs)} done")
                 active = keep
-            # 3. finished energies
-            for fut in [f for f in expecting if f.done()]:
-                a = expecting.pop(fut)
-                try:
-                    a.req.energy = float(fut.result())
-                    strings += a.frag.n_terms
-                except Exception as err:
-                    a.req.error = str(err)
-                a.req.finish = self.clock() - t0
-                self.resident_bytes[a.req.fid] = max(self.resident_bytes.get(a.req.fid, 0),
-                                                     self.backend.device_bytes(a.handle))
-                self._release(a, next_update)
-                done.append(a.req)
-            # 4. idle: wait for the next arrival or a finishing energy
-            if not active:
-                if expecting:
-                    cf.wait(list(expecting), timeout=0.05, return_when=cf.FIRST_COMPLETED)
-                elif stuck:
+            # 4. idle: wait for the next arrival
+            if not active and not ready:
+                if stuck:
                     r = waiting[0]
                     raise RuntimeError(f"request {r.rid} (fragment {r.fid}) cannot be admitted: "
                                        f"needs {self._need(self.frags[r.fid])} bytes, "
                                        f"budget {self.budget}")
-                elif upcoming:
+                if upcoming and not waiting:
                     self.sleep(max(0.0, min(0.05, upcoming[0].arrival - (self.clock() - t0))))
         span = max(r.finish for r in done) - min(r.arrival for r in done)
         return ServeReport(done, span, sum(1 for r in done if r.error is None), strings, max_seen,

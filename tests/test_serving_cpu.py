@@ -3,8 +3,6 @@ backend: admission by slots and memory budget, per-fragment update order,
 eviction of idle fragments, isolation of a failed request, and arrivals
 joining between gate chunks (continuous batching)."""
 
-import concurrent.futures as cf
-
 import numpy as np
 import pytest
 
@@ -54,15 +52,11 @@ class FakeBackend:
             raise err
         return np.array(done)
 
-    def submit_expect(self, h, frag):
-        f = cf.Future()
-        f.set_result(float(frag.fid) + 0.001 * h["applied"])
-        return f
+    def expect(self, h, frag):
+        return float(frag.fid) + 0.001 * h["applied"]
 
-    def submit_whole(self, h, frag, update):
-        f = cf.Future()
-        f.set_result(-1.0)
-        return f
+    def apply_all(self, h, frag, update):
+        h["applied"] += len(frag.updates[update][0])
 
     def device_bytes(self, h):
         return self.bytes
@@ -87,7 +81,7 @@ def test_all_complete_in_update_order():
     frags = _frags(4)
     reqs = make_requests(4, 3, rate=2000.0, rng=np.random.default_rng(1))
     be = FakeBackend()
-    rep = Server(frags, be, max_active=3, chunk=256).run(reqs)
+    rep = Server(frags, be, max_active=3, chunk=256, chunk_s=1e9, max_chunk=256).run(reqs)
     assert rep.completed == len(reqs)
     by_frag = {}
     for r in rep.requests:
@@ -136,7 +130,7 @@ def test_arrivals_join_between_chunks():
             return super().apply_chunk(items)
     be = SlowBackend()
     reqs = [Request(0, 0, 0, 0.0), Request(1, 1, 0, 0.03), Request(2, 2, 0, 0.06)]
-    rep = Server(frags, be, max_active=8, chunk=256).run(reqs)
+    rep = Server(frags, be, max_active=8, chunk=256, max_chunk=256).run(reqs)
     assert rep.completed == 3
     members = be.chunk_members
     assert (0,) in members and (0, 1) in members and (0, 1, 2) in members
@@ -164,3 +158,16 @@ def test_fragment_batchable_limit_and_estimate():
     f.max_bond = 128
     assert not f.batchable()
     assert estimate_bytes(24, 64, 1000) > estimate_bytes(24, 32, 1000) > 0
+
+
+def test_fragments_above_batched_limit_are_served_whole():
+    frags = _frags(2, gates_per_update=(400,), n_updates=1, qubits=16, bond=128)
+    frags += _frags(1, gates_per_update=(900,), n_updates=1)
+    frags[2].fid = 2
+    be = FakeBackend()
+    reqs = [Request(i, i, 0, 0.0) for i in range(3)]
+    rep = Server(frags, be, max_active=8, chunk=128, max_chunk=128).run(reqs)
+    assert rep.completed == 3
+    assert all(m == (2,) for m in be.chunk_members)  # only the batchable one is chunked
+    for r in rep.requests:
+        assert r.energy == pytest.approx(r.fid + 0.001 * frags[r.fid].updates[0][0].size)
