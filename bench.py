@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128", "split_bf16", "split_f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layers", type=int, default=None, help="override (smaller) layer count")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix sample")
@@ -208,6 +208,33 @@ def main():
     tm128 = m.timing()
     log(f"c128 step: {t128:.3f} s, E = {e128:.12f}")
 
+    # expectation phase alone on the final (canonical) state, every precision
+    precisions = {}
+    for pr in ("c128", "c64", "split_bf16", "split_f16"):
+        m.expect(plan, pr)  # setup for this precision (untimed)
+        m.set_timing(True)
+        torch.cuda.synchronize()
+        reps = 3
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            e_p = m.expect(plan, pr)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        tp = m.timing()
+        precisions[pr] = {
+            "expect_ms": 1e3 * dt,
+            "strings_per_s_expect": w.psum.n_terms / dt,
+            "env_kernels_ms": tp["env_ms"] / reps,
+            "env_tflops_algorithmic": (tp["env_flops"] / (tp["env_ms"] * 1e-3) / 1e12
+                                       if tp["env_ms"] > 0 else 0.0),
+            "energy": e_p,
+        }
+    e_ref = precisions["c128"]["energy"]
+    for pr, d in precisions.items():
+        d["abs_dE_vs_c128"] = abs(d["energy"] - e_ref)
+        log(f"expect {pr}: {d['expect_ms']:.1f} ms, env {d['env_tflops_algorithmic']:.1f} TFLOP/s, "
+            f"|dE| {d['abs_dE_vs_c128']:.2e}")
+
     K = args.steps
     ms_per_step = 1e3 * total / K
     value = w.psum.n_terms / (total / K)
@@ -261,6 +288,7 @@ def main():
                                   if tm["close_ms"] > 0 else 0.0),
                   "gflop_per_step": tm["close_flops"] / K / 1e9},
         "jacobi_sweeps_per_step": tm["jacobi_sweeps"] / K,
+        "expect_phase_by_precision": precisions,
         "plan": st,
         "bond_dims_max": int(dims.max()),
         "discarded_weight": disc,

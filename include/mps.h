@@ -58,13 +58,20 @@ typedef enum {
   MPS_ERR_STATE = -7      /* call not valid in the current state                */
 } mps_status;
 
-/* Arithmetic of the environment (transfer-matrix) products.  Gates, SVDs,
- * canonicalisation and the final energy sum are always FP64. */
+/* Arithmetic of the environment (transfer-matrix) products of Eq. (expec2).
+ * Gates, SVDs, canonicalisation and the final energy sum are always FP64.
+ * The split variants store environments in FP32 like C64 and evaluate the
+ * transfer-matrix products on 16-bit matrix cores: each FP32 operand x is
+ * split into a leading 16-bit part h and a trailing part l (x ~ h + l / S)
+ * and each real product is h h' + (h l' + l h') / S with FP32 accumulation
+ * (about 16 significant bits for bf16, S = 1; about 22 for f16, S = 2^11,
+ * which needs operands bounded by 1, as site tensors and environments are).
+ * Their closing traces run in FP32 as for C64. */
 typedef enum {
   MPS_PREC_C128 = 0,       /* complex128 on FP64 MFMA                              */
   MPS_PREC_C64 = 1,        /* complex64 on FP32 MFMA                               */
-  MPS_PREC_SPLIT_BF16 = 2, /* FP32 values split into bf16 hi+lo, FP32 accumulate   */
-  MPS_PREC_SPLIT_F16 = 3   /* FP32 values split into scaled f16 hi+lo, FP32 accum. */
+  MPS_PREC_SPLIT_BF16 = 2, /* FP32 split into bf16 h + l, bf16 MFMA, FP32 accumulate */
+  MPS_PREC_SPLIT_F16 = 3   /* FP32 split into f16 h + l/2^11, f16 MFMA, FP32 accum.  */
 } mps_precision;
 
 typedef struct {
@@ -236,10 +243,12 @@ mps_status mps_get_timing(mps_handle h, mps_timing* out);
 mps_status mps_device_bytes(mps_handle h, size_t* bytes);
 
 /* Layout self-check of the matrix-core instructions used by the dense
- * products: runs one 16x16x4 product of known operands in FP64 and in FP32
- * on the device and writes each 16x16 result, read back through the lane
- * layout the kernels assume, to out (2 x 256 doubles, row-major: FP64 first,
- * then FP32). */
+ * products: runs one product of known operands per instruction (FP64 and
+ * FP32 16x16x4, bf16 and f16 16x16x32) on the device and writes each 16x16
+ * result, read back through the lane
+ * layout the kernels assume, to out (4 x 256 doubles, row-major: FP64
+ * 16x16x4, FP32 16x16x4, then bf16 and f16 16x16x32 with
+ * A[i][k] = ((i + 2k) mod 7) - 3 and B[k][j] = ((3k + j) mod 5) - 2). */
 mps_status mps_selftest_mfma(double* out);
 
 /* Thread-local description of the last error on this thread. */

@@ -355,8 +355,9 @@ def jacobi_svd(vectors: np.ndarray):
 
 
 def selftest_mfma() -> np.ndarray:
-    """(2, 16, 16): the FP64 and FP32 16x16x4 products of the layout check."""
+    """(4, 16, 16): the FP64 and FP32 16x16x4 and the bf16 and f16 16x16x32
+    products of the layout check."""
     lib = load()
-    out = np.zeros((2, 16, 16), np.float64)
+    out = np.zeros((4, 16, 16), np.float64)
     _check(lib.mps_selftest_mfma(_ptr(out)))
     return out

@@ -191,6 +191,11 @@ hipError_t launch_env_gemm1_c64(const EnvParent<float2>* items, int count, const
 hipError_t launch_env_gemm2_c64(const EnvChild<float2>* items, int count, const float2* site,
                                 int dl, int dr, hipStream_t s);
 
+hipError_t launch_env_gemm1_split(const EnvParent<float2>* items, int count, const float2* site, int dl,
+                                  int dr, int f16, hipStream_t s);
+hipError_t launch_env_gemm2_split(const EnvChild<float2>* items, int count, const float2* site, int dl,
+                                  int dr, int f16, hipStream_t s);
+
 hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr, int dl, int dr,
                                int elem_bytes, hipStream_t s);
 hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,

@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "gemm_core.h"
+#include "gemm_split.h"
 #include "internal.h"
 #include "wave_ops.h"
 
@@ -945,6 +946,20 @@ hipError_t launch_env_gemm2_c64(const EnvChild<float2>* items, int count, const 
   return launch_cgemm<64, 64, 16>(p, count, dr, dr, s);
 }
 
+// split precisions: FP32 environments, 16-bit matrix cores, FP32 accumulation
+hipError_t launch_env_gemm1_split(const EnvParent<float2>* items, int count, const float2* site, int dl,
+                                  int dr, int f16, hipStream_t s) {
+  EnvG1P<float> p{items, site, dl, dr};
+  return f16 ? launch_cgemm_split<_Float16, 64, 64>(p, count, dl, 2 * dr, s)
+             : launch_cgemm_split<__bf16, 64, 64>(p, count, dl, 2 * dr, s);
+}
+hipError_t launch_env_gemm2_split(const EnvChild<float2>* items, int count, const float2* site, int dl,
+                                  int dr, int f16, hipStream_t s) {
+  EnvG2P<float> p{items, site, dl, dr};
+  return f16 ? launch_cgemm_split<_Float16, 64, 64>(p, count, dr, dr, s)
+             : launch_cgemm_split<__bf16, 64, 64>(p, count, dr, dr, s);
+}
+
 // Site tensor in the environment precision (fwd, may be null) and its
 // per-letter transpose tr[s][beta][alpha] = B[s][alpha][beta], which turns the
 // right update R' = sum sigma B^{s'} R B^{s+} into the left form on R^T.
@@ -1129,10 +1144,27 @@ __global__ void selftest_mfma_kernel(double* out) {
   acc = mfma_16x16x4(a, b, acc);
   f4_t facc = {0.f, 0.f, 0.f, 0.f};
   facc = mfma_16x16x4((float)a, (float)b, facc);
+  // 16x16x32: A[i][kk] = ((i + 2 kk) mod 7) - 3, B[kk][j] = ((3 kk + j) mod 5) - 2 (exact in 16 bits)
+  bf16x8_t ab, bb;
+  f16x8_t ah, bh;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kk = frag32_k(l, j);
+    const float av = (float)(((r + 2 * kk) % 7) - 3), bv = (float)(((3 * kk + r) % 5) - 2);
+    ab[j] = (__bf16)av;
+    bb[j] = (__bf16)bv;
+    ah[j] = (_Float16)av;
+    bh[j] = (_Float16)bv;
+  }
+  f4_t c16 = {0.f, 0.f, 0.f, 0.f}, d16 = {0.f, 0.f, 0.f, 0.f};
+  c16 = split_traits<__bf16>::mfma(ab, bb, c16);
+  d16 = split_traits<_Float16>::mfma(ah, bh, d16);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     out[acc_row<double>(k, v) * 16 + r] = acc[v];
     out[256 + acc_row<float>(k, v) * 16 + r] = (double)facc[v];
+    out[512 + acc_row<float>(k, v) * 16 + r] = (double)c16[v];
+    out[768 + acc_row<float>(k, v) * 16 + r] = (double)d16[v];
   }
 }
 

@@ -997,11 +997,17 @@ mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int pre
                                      (const double2*)site_ptr, L.dl, L.dr, h->stream));
     HIP_TRY(h, launch_env_gemm2_c128((const EnvChild<double2>*)(db + L.children_off), L.n_children,
                                      (const double2*)site_ptr, L.dl, L.dr, h->stream));
-  } else {
+  } else if (prec == MPS_PREC_C64) {
     HIP_TRY(h, launch_env_gemm1_c64((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
                                     (const float2*)site_ptr, L.dl, L.dr, h->stream));
     HIP_TRY(h, launch_env_gemm2_c64((const EnvChild<float2>*)(db + L.children_off), L.n_children,
                                     (const float2*)site_ptr, L.dl, L.dr, h->stream));
+  } else {
+    const int f16 = prec == MPS_PREC_SPLIT_F16;
+    HIP_TRY(h, launch_env_gemm1_split((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
+                                      (const float2*)site_ptr, L.dl, L.dr, f16, h->stream));
+    HIP_TRY(h, launch_env_gemm2_split((const EnvChild<float2>*)(db + L.children_off), L.n_children,
+                                      (const float2*)site_ptr, L.dl, L.dr, f16, h->stream));
   }
   if (h->timing) {
     HIP_TRY(h, hipEventRecord(e, h->stream));
@@ -1542,8 +1548,9 @@ mps_status mps_expect_pauli_sum(mps_handle h, mps_pauli_sum p, mps_precision pre
   if (st != MPS_OK) return st;
   if (!p || !energy) return fail(MPS_ERR_ARG, "NULL plan or output");
   if (p->plan.n_qubits != h->n) return fail(MPS_ERR_ARG, "plan and MPS qubit counts differ");
-  if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64)
-    return fail(MPS_ERR_ARG, "precision not available (c128 and c64 are implemented)");
+  if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64 && prec != MPS_PREC_SPLIT_BF16 &&
+      prec != MPS_PREC_SPLIT_F16)
+    return fail(MPS_ERR_ARG, "unknown precision");
   return expect_impl(h, p, (int)prec, energy, per_term);
 }
 
@@ -1703,10 +1710,10 @@ mps_status mps_device_bytes(mps_handle h, size_t* bytes) {
 mps_status mps_selftest_mfma(double* out) {
   if (!out) return fail(MPS_ERR_ARG, "NULL output");
   double* d = nullptr;
-  hipError_t e = hipMalloc((void**)&d, 512 * sizeof(double));
+  hipError_t e = hipMalloc((void**)&d, 1024 * sizeof(double));
   if (e != hipSuccess) return fail(MPS_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = launch_selftest_mfma(d, nullptr);
-  if (e == hipSuccess) e = hipMemcpy(out, d, 512 * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(out, d, 1024 * sizeof(double), hipMemcpyDeviceToHost);
   (void)hipFree(d);
   if (e != hipSuccess) return fail(MPS_ERR_DEVICE, std::string("selftest: ") + hipGetErrorString(e));
   return MPS_OK;
