@@ -25,6 +25,7 @@
 #include <utility>
 
 #include "internal.h"
+#include "jacobi_ops.h"
 #include "wave_ops.h"
 
 namespace mps {
@@ -45,65 +46,6 @@ __device__ __forceinline__ int pos_id(int p, int r, int nb) {
 constexpr int rr8(int p, int s) { return p == 0 ? 0 : 1 + ((p - 1 + s) % 7); }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a < b ? b : a; }
-
-template <int E>
-__device__ __forceinline__ void pair_partials(const double2 (&x)[E], const double2 (&y)[E],
-                                              double* acc) {
-  double xx = 0.0, yy = 0.0, re = 0.0, im = 0.0;
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const double2 a = x[k], b = y[k];
-    xx += a.x * a.x + a.y * a.y;
-    yy += b.x * b.x + b.y * b.y;
-    re += a.x * b.x + a.y * b.y;
-    im += a.x * b.y - a.y * b.x;
-  }
-  acc[0] = xx;
-  acc[1] = yy;
-  acc[2] = re;
-  acc[3] = im;
-}
-
-struct Rot {
-  double c, ar, ai, br, bi;  // x' = c x + (ar + i ai) y,  y' = c y + (br + i bi) x
-};
-
-// Algorithm 1's rotation for the reduced (x^+x, y^+y, Re x^+y, Im x^+y) of
-// one pair, in this lane; the row with the lower index plays a_i.  Returns
-// false when the pair is already orthogonal to the tolerance
-// (|b_ij| <= eps sqrt(b_ii b_jj) or <= floor).
-__device__ __forceinline__ bool pair_rot_lane(const double* acc, bool x_is_i, double eps,
-                                              double floor, Rot& rt) {
-  const double bxx = acc[0], byy = acc[1], br = acc[2], bi = acc[3];
-  const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
-  const double mag = sqrt(br * br + bi * bi);
-  if (!(mag > floor) || !(mag > eps * sqrt(bii * bjj))) return false;
-  const double tau = (bii - bjj) / (2.0 * mag);
-  const double at = fabs(tau);
-  const double sg = tau >= 0.0 ? 1.0 : -1.0;
-  const double t = at > 1e100 ? sg * (0.5 / at) : sg / (at + sqrt(1.0 + tau * tau));
-  const double c = 1.0 / sqrt(1.0 + t * t);
-  const double s = t * c;
-  const double er = br / mag, ei = x_is_i ? bi / mag : -bi / mag;
-  // a_i' = c a_i + s conj(e) a_j,  a_j' = c a_j - s e a_i
-  const double pr = s * er, pi = -s * ei, qr = -s * er, qi = -s * ei;
-  rt.c = c;
-  rt.ar = x_is_i ? pr : qr;
-  rt.ai = x_is_i ? pi : qi;
-  rt.br = x_is_i ? qr : pr;
-  rt.bi = x_is_i ? qi : pi;
-  return true;
-}
-
-template <int E>
-__device__ __forceinline__ void pair_apply(double2 (&x)[E], double2 (&y)[E], const Rot& rt) {
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const double2 a = x[k], b = y[k];
-    x[k] = make_double2(rt.c * a.x + (rt.ar * b.x - rt.ai * b.y), rt.c * a.y + (rt.ar * b.y + rt.ai * b.x));
-    y[k] = make_double2(rt.c * b.x + (rt.br * a.x - rt.bi * a.y), rt.c * b.y + (rt.br * a.y + rt.bi * a.x));
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Eight pairs at a time.  The 32 per-lane partial sums (x^+x, y^+y, Re x^+y,
@@ -141,21 +83,6 @@ __device__ __forceinline__ double2 (&blk(double2 (&T)[FB][E], double2 (&B)[FB][E
 template <int H>
 __device__ __forceinline__ double rs_pick(const double (&v)[2 * H], int j, bool hi, bool send) {
   return (hi != send) ? v[H + j] : v[j];
-}
-
-template <int PAT>
-__device__ __forceinline__ double swizzle(double x) {
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), PAT);
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), PAT);
-  return __hiloint2double(hi, lo);
-}
-// ds_swizzle bit mode: lane' = ((lane & and) | or) ^ xor within 32 lanes
-constexpr int swz(int x) { return 0x1F | (x << 10); }
-
-__device__ __forceinline__ double readlane_d(double x, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-  return __hiloint2double(hi, lo);
 }
 
 template <int E, class P, int I>

@@ -1,0 +1,89 @@
+// Algorithm 1's pair step on register-resident rows, shared by the Jacobi
+// kernels: partial sums of (x^+x, y^+y, x^+y) per lane, the rotation of one
+// pair from the reduced sums, and its application; plus the lane-exchange
+// helpers used to reduce several pairs at once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wave_ops.h"
+
+namespace mps {
+
+template <int E>
+__device__ __forceinline__ void pair_partials(const double2 (&x)[E], const double2 (&y)[E],
+                                              double* acc) {
+  double xx = 0.0, yy = 0.0, re = 0.0, im = 0.0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 a = x[k], b = y[k];
+    xx += a.x * a.x + a.y * a.y;
+    yy += b.x * b.x + b.y * b.y;
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  acc[0] = xx;
+  acc[1] = yy;
+  acc[2] = re;
+  acc[3] = im;
+}
+
+struct Rot {
+  double c, ar, ai, br, bi;  // x' = c x + (ar + i ai) y,  y' = c y + (br + i bi) x
+};
+
+// Algorithm 1's rotation for the reduced (x^+x, y^+y, Re x^+y, Im x^+y) of
+// one pair, in this lane; the row with the lower index plays a_i.  Returns
+// false when the pair is already orthogonal to the tolerance
+// (|b_ij| <= eps sqrt(b_ii b_jj) or <= floor).
+__device__ __forceinline__ bool pair_rot_lane(const double* acc, bool x_is_i, double eps,
+                                              double floor, Rot& rt) {
+  const double bxx = acc[0], byy = acc[1], br = acc[2], bi = acc[3];
+  const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
+  // |b_ij| > floor and |b_ij| > eps sqrt(b_ii b_jj), compared in squares
+  const double mag2 = br * br + bi * bi;
+  if (!(mag2 > floor * floor) || !(mag2 > eps * eps * (bii * bjj))) return false;
+  const double rinv = rsqrt(mag2);  // 1 / |b_ij|
+  const double tau = (bii - bjj) * (0.5 * rinv);
+  const double at = fabs(tau);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  const double t = at > 1e100 ? sg * (0.5 / at) : sg / (at + sqrt(1.0 + tau * tau));
+  const double c = rsqrt(1.0 + t * t);
+  const double s = t * c;
+  const double er = br * rinv, ei = x_is_i ? bi * rinv : -bi * rinv;
+  // a_i' = c a_i + s conj(e) a_j,  a_j' = c a_j - s e a_i
+  const double pr = s * er, pi = -s * ei, qr = -s * er, qi = -s * ei;
+  rt.c = c;
+  rt.ar = x_is_i ? pr : qr;
+  rt.ai = x_is_i ? pi : qi;
+  rt.br = x_is_i ? qr : pr;
+  rt.bi = x_is_i ? qi : pi;
+  return true;
+}
+
+template <int E>
+__device__ __forceinline__ void pair_apply(double2 (&x)[E], double2 (&y)[E], const Rot& rt) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 a = x[k], b = y[k];
+    x[k] = make_double2(rt.c * a.x + (rt.ar * b.x - rt.ai * b.y), rt.c * a.y + (rt.ar * b.y + rt.ai * b.x));
+    y[k] = make_double2(rt.c * b.x + (rt.br * a.x - rt.bi * a.y), rt.c * b.y + (rt.br * a.y + rt.bi * a.x));
+  }
+}
+
+template <int PAT>
+__device__ __forceinline__ double swizzle(double x) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), PAT);
+  return __hiloint2double(hi, lo);
+}
+// ds_swizzle bit mode: lane' = ((lane & and) | or) ^ xor within 32 lanes
+constexpr int swz(int x) { return 0x1F | (x << 10); }
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+}  // namespace mps

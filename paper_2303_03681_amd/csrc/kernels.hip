@@ -20,6 +20,7 @@
 #include "gemm_core.h"
 #include "gemm_split.h"
 #include "internal.h"
+#include "jacobi_ops.h"
 #include "wave_ops.h"
 
 namespace mps {
@@ -440,42 +441,127 @@ __global__ __launch_bounds__(JW * 64) void jacobi_reg_full_kernel(const JacItem*
   reg_epilogue<E>(c, rot, &s_rot, x, gx, y, gy, sweep);
 }
 
-// Outer rounds >= 1: the 64 cross pairs of blocks bp and bq.  Wave i keeps
-// resident vector bp*8 + i; the travellers from block bq move one wave along
-// per inner round through 8 LDS slots.
+// Two disjoint pairs (x0, y0), (x1, y1) of one wave at once: the 8 partial
+// sums are reduce-scattered over the wave (lane bits 3, 2, 1 by DPP halving,
+// then full sums over bits 0, 4, 5), so lane l holds component
+// ((l >> 2) & 3) of pair ((l >> 1) & 1); the four components of its pair are
+// gathered by swizzles and the rotation is computed lane-parallel; the two
+// coefficient sets then go to scalar registers.  The same bits reach every
+// lane that holds a pair's sums.
 template <int E>
-__global__ __launch_bounds__(JW * 64, 4) void jacobi_reg_cross_kernel(const JacItem* items, int max_pairs,
-                                                                   int round, int sweep,
-                                                                   double eps_scale) {
-  extern __shared__ double2 slots[];  // JW slots of 64 * E elements
+__device__ __forceinline__ int rot2(RegVec<E>& x0, RegVec<E>& y0, RegVec<E>& x1, RegVec<E>& y1,
+                                    bool x_is_i, double eps, double floor, int lane) {
+  double v[8];  // v[2c + i]: component c of pair i
+  {
+    double a[4], b[4];
+    pair_partials<E>(x0.v, y0.v, a);
+    pair_partials<E>(x1.v, y1.v, b);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      v[2 * c] = a[c];
+      v[2 * c + 1] = b[c];
+    }
+  }
+  double v4[4], v2[2], x;
+  {
+    const bool hi = (lane >> 3) & 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v4[j] = (hi ? v[4 + j] : v[j]) + dpp_mov<0x140>(hi ? v[j] : v[4 + j]);
+  }
+  {
+    const bool hi = (lane >> 2) & 1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      v2[j] = (hi ? v4[2 + j] : v4[j]) + dpp_mov<0x141>(hi ? v4[j] : v4[2 + j]);
+  }
+  {
+    const bool hi = (lane >> 1) & 1;
+    x = (hi ? v2[1] : v2[0]) + dpp_mov<0x4E>(hi ? v2[0] : v2[1]);
+  }
+  x += dpp_mov<0xB1>(x);
+  x += swizzle<swz(16)>(x);
+  x += __shfl_xor(x, 32, 64);
+  const double x4 = swizzle<swz(4)>(x);
+  const double x8 = swizzle<swz(8)>(x);
+  const double x12 = swizzle<swz(12)>(x);
+  const int c = (lane >> 2) & 3;
+  const double acc[4] = {c == 0 ? x : c == 1 ? x4 : c == 2 ? x8 : x12,
+                         c == 1 ? x : c == 0 ? x4 : c == 3 ? x8 : x12,
+                         c == 2 ? x : c == 3 ? x4 : c == 0 ? x8 : x12,
+                         c == 3 ? x : c == 2 ? x4 : c == 1 ? x8 : x12};
+  Rot mine{1.0, 0.0, 0.0, 0.0, 0.0};
+  const uint64_t act = __ballot(pair_rot_lane(acc, x_is_i, eps, floor, mine));
+  int rot = 0;
+  // pair i is held (components 0) by lane 2 i
+  if (act & 1ull) {
+    const Rot rt{readlane_d(mine.c, 0), readlane_d(mine.ar, 0), readlane_d(mine.ai, 0),
+                 readlane_d(mine.br, 0), readlane_d(mine.bi, 0)};
+    pair_apply<E>(x0.v, y0.v, rt);
+    ++rot;
+  }
+  if (act & 4ull) {
+    const Rot rt{readlane_d(mine.c, 2), readlane_d(mine.ar, 2), readlane_d(mine.ai, 2),
+                 readlane_d(mine.br, 2), readlane_d(mine.bi, 2)};
+    pair_apply<E>(x1.v, y1.v, rt);
+    ++rot;
+  }
+  return rot;
+}
+
+// Outer rounds >= 1: the 64 cross pairs of blocks bp and bq on CW = 4 waves.
+// Wave w keeps resident rows bp*8 + 2w, 2w + 1 and holds two travellers from
+// block bq, which move one wave along per step through LDS (4 steps); each
+// step is two sub-steps of two disjoint pairs.
+constexpr int CW = 4;
+
+template <int E>
+__global__ __launch_bounds__(CW * 64, 2) void jacobi_reg_cross_kernel(const JacItem* items, int max_pairs,
+                                                                      int round, int sweep,
+                                                                      double eps_scale) {
+  extern __shared__ double2 slots[];  // CW slots of two travellers (2 x 64 E elements)
   __shared__ int s_rot;
   RegCtx c;
   if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
   const int m = c.it.m, n = c.it.n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) s_rot = 0;
-  RegVec<E> x, y;
-  int gx = c.bp * JW + wv;
-  gx = gx < n ? gx : -1;
-  int src = wv;  // home wave of the traveller currently held
-  int gy = c.bq * JW + src;
-  gy = gy < n ? gy : -1;
-  rv_load<E>(x, c.it.w + (size_t)max(gx, 0) * m, gx >= 0, m, lane);
-  rv_load<E>(y, c.it.w + (size_t)max(gy, 0) * m, gy >= 0, m, lane);
+  RegVec<E> r0, r1, t0, t1;
+  const int g0 = c.bp * JW + 2 * wv, g1 = g0 + 1;
+  rv_load<E>(r0, c.it.w + (size_t)min(g0, n - 1) * m, g0 < n, m, lane);
+  rv_load<E>(r1, c.it.w + (size_t)min(g1, n - 1) * m, g1 < n, m, lane);
+  int src = wv;  // home wave of the travellers held
+  {
+    const int h0 = c.bq * JW + 2 * src, h1 = h0 + 1;
+    rv_load<E>(t0, c.it.w + (size_t)min(h0, n - 1) * m, h0 < n, m, lane);
+    rv_load<E>(t1, c.it.w + (size_t)min(h1, n - 1) * m, h1 < n, m, lane);
+  }
+  const bool x_is_i = c.bp < c.bq;
   int rot = 0;
-  for (int t = 0; t < JW; ++t) {
-    rot += jacobi_pair_ordered<E>(x, gx, y, gy, c.eps, c.floor);
-    if (t == JW - 1) break;
-    rv_to_lds<E>(y, slots + (size_t)wv * 64 * E, lane);
+  for (int st = 0; st < CW; ++st) {
+    rot += rot2<E>(r0, t0, r1, t1, x_is_i, c.eps, c.floor, lane);
+    rot += rot2<E>(r0, t1, r1, t0, x_is_i, c.eps, c.floor, lane);
+    if (st == CW - 1) break;
+    double2* mine = slots + (size_t)wv * 2 * 64 * E;
+    rv_to_lds<E>(t0, mine, lane);
+    rv_to_lds<E>(t1, mine + 64 * E, lane);
     __syncthreads();
-    rv_from_lds<E>(y, slots + (size_t)((wv + JW - 1) % JW) * 64 * E, lane);
-    src = (src + JW - 1) % JW;
-    gy = c.bq * JW + src;
-    gy = gy < n ? gy : -1;
+    const double2* prev = slots + (size_t)((wv + CW - 1) % CW) * 2 * 64 * E;
+    rv_from_lds<E>(t0, prev, lane);
+    rv_from_lds<E>(t1, prev + 64 * E, lane);
+    src = (src + CW - 1) % CW;
     __syncthreads();
   }
+  if (lane == 0 && rot) atomicAdd(&s_rot, rot);
   __syncthreads();
-  reg_epilogue<E>(c, rot, &s_rot, x, gx, y, gy, sweep);
+  if (s_rot > 0) {
+    const int h0 = c.bq * JW + 2 * src, h1 = h0 + 1;
+    if (g0 < n) rv_store<E>(r0, c.it.w + (size_t)g0 * m, m, lane);
+    if (g1 < n) rv_store<E>(r1, c.it.w + (size_t)g1 * m, m, lane);
+    if (h0 < n) rv_store<E>(t0, c.it.w + (size_t)h0 * m, m, lane);
+    if (h1 < n) rv_store<E>(t1, c.it.w + (size_t)h1 * m, m, lane);
+    if (threadIdx.x == 0) atomicAdd(&c.it.rot[sweep * c.it.rot_stride], s_rot);
+  }
 }
 
 template <int E>
@@ -486,8 +572,8 @@ hipError_t launch_reg_e(const JacItem* items_dev, int items, int max_pairs, int 
     hipLaunchKernelGGL(jacobi_reg_full_kernel<E>, grid, block, 2 * JW * 64 * E * sizeof(double2), s,
                        items_dev, max_pairs, round, sweep, eps_scale);
   else
-    hipLaunchKernelGGL(jacobi_reg_cross_kernel<E>, grid, block, JW * 64 * E * sizeof(double2), s,
-                       items_dev, max_pairs, round, sweep, eps_scale);
+    hipLaunchKernelGGL(jacobi_reg_cross_kernel<E>, grid, dim3(CW * 64), CW * 2 * 64 * E * sizeof(double2),
+                       s, items_dev, max_pairs, round, sweep, eps_scale);
   return hipGetLastError();
 }
 
