@@ -34,6 +34,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}  # MI355X dense FP64 / FP32 matrix peaks
+# HBM bytes per environment launch on this workload from two rocprofv3 --pmc passes
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by a 256 MiB copy), environment kernels
+# unchanged since; profiles/env_gemm_traffic_50q_D256.md has the commands and figures.
+ENV_TRAFFIC_BYTES = {"c64": 428.2e6, "c128": 933.1e6, "split_bf16": 429.0e6, "split_f16": 429.0e6}
 METRIC = "Pauli-string expectations/s at 50q D=256 vs complex128 path; p50/p99 latency"
 
 
@@ -134,6 +138,9 @@ def main():
     ap.add_argument("--layers", type=int, default=None, help="override (smaller) layer count")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix sample")
     ap.add_argument("--serving-fragments", type=int, default=8)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a plain copy of known "
+                         "size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus "
@@ -150,6 +157,15 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 18  # float32 elements
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.calibrate_copy} MiB read + written")
+        del src, dst
 
     t0 = time.perf_counter()
     w = build_config(3, layers=args.layers)
@@ -247,7 +263,8 @@ def main():
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": env_tflops / peak,
-        "traffic": None,
+        "traffic": ENV_TRAFFIC_BYTES.get(args.prec),
+        "traffic_unit": "bytes per launch (HBM, scaled PMC FETCH_SIZE + WRITE_SIZE)",
         "kernel": "cgemm_kernel<EnvG1P/EnvG2P> (transfer-matrix update)",
         "flops_per_launch": tm["env_flops"] / max(1, tm["env_launches"]),
         "avg_launch_ms": tm["env_ms"] / max(1, tm["env_launches"]),

@@ -328,8 +328,13 @@ constexpr int kSmallMax = 128;   // rows and row length of the one-workgroup reg
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
+  // One workgroup per matrix: for batches of small matrices only, and for
+  // tiny ones in any batch (a 128 x 128 item on one CU would otherwise hold
+  // up the multi-workgroup rounds of the large items queued after it).
+  bool all_small = true;
+  for (const JacItem& it : all) all_small = all_small && it.n <= kSmallMax && it.m <= kSmallMax;
   for (JacItem it : all) {
-    if (it.n <= kSmallMax && it.m <= kSmallMax) {
+    if (it.n <= kSmallMax && it.m <= kSmallMax && (all_small || it.n * it.m <= 64 * 64)) {
       jp.small.push_back(it);
       continue;
     }
