@@ -32,13 +32,13 @@ struct Rot {
   double c, ar, ai, br, bi;  // x' = c x + (ar + i ai) y,  y' = c y + (br + i bi) x
 };
 
-// Algorithm 1's rotation for the reduced (x^+x, y^+y, Re x^+y, Im x^+y) of
-// one pair, in this lane; the row with the lower index plays a_i.  Returns
-// false when the pair is already orthogonal to the tolerance
-// (|b_ij| <= eps sqrt(b_ii b_jj) or <= floor).
-__device__ __forceinline__ bool pair_rot_lane(const double* acc, bool x_is_i, double eps,
-                                              double floor, Rot& rt) {
-  const double bxx = acc[0], byy = acc[1], br = acc[2], bi = acc[3];
+// Algorithm 1's rotation from b_xx = x^+x, b_yy = y^+y and b_xy = x^+y of one
+// pair, in this lane; the row with the lower index plays a_i.  Returns false
+// when the pair is already orthogonal to the tolerance (|b_ij| <= eps
+// sqrt(b_ii b_jj) or <= floor).  *dn receives t |b_ij|, by which b_ii grows
+// and b_jj shrinks under the rotation.
+__device__ __forceinline__ bool pair_rot_core(double bxx, double byy, double br, double bi, bool x_is_i,
+                                              double eps, double floor, Rot& rt, double* dn) {
   const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
   // |b_ij| > floor and |b_ij| > eps sqrt(b_ii b_jj), compared in squares
   const double mag2 = br * br + bi * bi;
@@ -58,7 +58,28 @@ __device__ __forceinline__ bool pair_rot_lane(const double* acc, bool x_is_i, do
   rt.ai = x_is_i ? pi : qi;
   rt.br = x_is_i ? qr : pr;
   rt.bi = x_is_i ? qi : pi;
+  if (dn) *dn = t * (mag2 * rinv);
   return true;
+}
+
+// The same from the reduced (x^+x, y^+y, Re x^+y, Im x^+y).
+__device__ __forceinline__ bool pair_rot_lane(const double* acc, bool x_is_i, double eps,
+                                              double floor, Rot& rt) {
+  return pair_rot_core(acc[0], acc[1], acc[2], acc[3], x_is_i, eps, floor, rt, nullptr);
+}
+
+// Partial sums of Re and Im of x^+y over this lane's elements.
+template <int E>
+__device__ __forceinline__ void pair_partials_xy(const double2 (&x)[E], const double2 (&y)[E],
+                                                 double& re, double& im) {
+  re = 0.0;
+  im = 0.0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const double2 a = x[k], b = y[k];
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
 }
 
 template <int E>

@@ -441,78 +441,78 @@ __global__ __launch_bounds__(JW * 64) void jacobi_reg_full_kernel(const JacItem*
   reg_epilogue<E>(c, rot, &s_rot, x, gx, y, gy, sweep);
 }
 
-// Two disjoint pairs (x0, y0), (x1, y1) of one wave at once: the 8 partial
-// sums are reduce-scattered over the wave (lane bits 3, 2, 1 by DPP halving,
-// then full sums over bits 0, 4, 5), so lane l holds component
-// ((l >> 2) & 3) of pair ((l >> 1) & 1); the four components of its pair are
-// gathered by swizzles and the rotation is computed lane-parallel; the two
-// coefficient sets then go to scalar registers.  The same bits reach every
-// lane that holds a pair's sums.
+// Two disjoint pairs (x0, y0), (x1, y1) with their squared norms tracked:
+// only x^+y is reduced (4 partial sums, reduce-scattered over lane bits 3
+// and 2, then full sums over bits 1, 0, 4, 5), so lane l holds component
+// (l >> 3) & 1 (Re, Im) of pair (l >> 2) & 1; the other component comes by a
+// swizzle, the rotation is computed lane-parallel and the norms move by
+// +-t |b_ij| (Algorithm 1 recomputes them; the caller does so at every
+// launch, so at most a few updates accumulate).
 template <int E>
-__device__ __forceinline__ int rot2(RegVec<E>& x0, RegVec<E>& y0, RegVec<E>& x1, RegVec<E>& y1,
-                                    bool x_is_i, double eps, double floor, int lane) {
-  double v[8];  // v[2c + i]: component c of pair i
-  {
-    double a[4], b[4];
-    pair_partials<E>(x0.v, y0.v, a);
-    pair_partials<E>(x1.v, y1.v, b);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      v[2 * c] = a[c];
-      v[2 * c + 1] = b[c];
-    }
-  }
-  double v4[4], v2[2], x;
+__device__ __forceinline__ int rot2n(RegVec<E>& x0, RegVec<E>& y0, double& nx0, double& ny0,
+                                     RegVec<E>& x1, RegVec<E>& y1, double& nx1, double& ny1,
+                                     bool x_is_i, double eps, double floor, int lane) {
+  double v[4];  // v[2c + i]: component c (0 Re, 1 Im) of pair i
+  pair_partials_xy<E>(x0.v, y0.v, v[0], v[2]);
+  pair_partials_xy<E>(x1.v, y1.v, v[1], v[3]);
+  double v2[2], x;
   {
     const bool hi = (lane >> 3) & 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      v4[j] = (hi ? v[4 + j] : v[j]) + dpp_mov<0x140>(hi ? v[j] : v[4 + j]);
+    for (int j = 0; j < 2; ++j)
+      v2[j] = (hi ? v[2 + j] : v[j]) + dpp_mov<0x140>(hi ? v[j] : v[2 + j]);
   }
   {
     const bool hi = (lane >> 2) & 1;
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      v2[j] = (hi ? v4[2 + j] : v4[j]) + dpp_mov<0x141>(hi ? v4[j] : v4[2 + j]);
+    x = (hi ? v2[1] : v2[0]) + dpp_mov<0x141>(hi ? v2[0] : v2[1]);
   }
-  {
-    const bool hi = (lane >> 1) & 1;
-    x = (hi ? v2[1] : v2[0]) + dpp_mov<0x4E>(hi ? v2[0] : v2[1]);
-  }
+  x += dpp_mov<0x4E>(x);
   x += dpp_mov<0xB1>(x);
   x += swizzle<swz(16)>(x);
   x += __shfl_xor(x, 32, 64);
-  const double x4 = swizzle<swz(4)>(x);
-  const double x8 = swizzle<swz(8)>(x);
-  const double x12 = swizzle<swz(12)>(x);
-  const int c = (lane >> 2) & 3;
-  const double acc[4] = {c == 0 ? x : c == 1 ? x4 : c == 2 ? x8 : x12,
-                         c == 1 ? x : c == 0 ? x4 : c == 3 ? x8 : x12,
-                         c == 2 ? x : c == 3 ? x4 : c == 0 ? x8 : x12,
-                         c == 3 ? x : c == 2 ? x4 : c == 1 ? x8 : x12};
+  const double other = swizzle<swz(8)>(x);
+  const bool im_lane = (lane >> 3) & 1;
+  const bool p1 = (lane >> 2) & 1;
   Rot mine{1.0, 0.0, 0.0, 0.0, 0.0};
-  const uint64_t act = __ballot(pair_rot_lane(acc, x_is_i, eps, floor, mine));
+  double dn = 0.0;
+  const bool a = pair_rot_core(p1 ? nx1 : nx0, p1 ? ny1 : ny0, im_lane ? other : x, im_lane ? x : other,
+                               x_is_i, eps, floor, mine, &dn);
+  const uint64_t act = __ballot(a);
   int rot = 0;
-  // pair i is held (components 0) by lane 2 i
+  // pair i is held (Re component) by lane 4 i
   if (act & 1ull) {
     const Rot rt{readlane_d(mine.c, 0), readlane_d(mine.ar, 0), readlane_d(mine.ai, 0),
                  readlane_d(mine.br, 0), readlane_d(mine.bi, 0)};
+    const double d = readlane_d(dn, 0);
     pair_apply<E>(x0.v, y0.v, rt);
+    nx0 += x_is_i ? d : -d;
+    ny0 -= x_is_i ? d : -d;
     ++rot;
   }
-  if (act & 4ull) {
-    const Rot rt{readlane_d(mine.c, 2), readlane_d(mine.ar, 2), readlane_d(mine.ai, 2),
-                 readlane_d(mine.br, 2), readlane_d(mine.bi, 2)};
+  if (act & 16ull) {
+    const Rot rt{readlane_d(mine.c, 4), readlane_d(mine.ar, 4), readlane_d(mine.ai, 4),
+                 readlane_d(mine.br, 4), readlane_d(mine.bi, 4)};
+    const double d = readlane_d(dn, 4);
     pair_apply<E>(x1.v, y1.v, rt);
+    nx1 += x_is_i ? d : -d;
+    ny1 -= x_is_i ? d : -d;
     ++rot;
   }
   return rot;
 }
 
+template <int E>
+__device__ __forceinline__ double rv_norm2(const RegVec<E>& r) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) s += r.v[k].x * r.v[k].x + r.v[k].y * r.v[k].y;
+  return wave_sum(s);
+}
+
 // Outer rounds >= 1: the 64 cross pairs of blocks bp and bq on CW = 4 waves.
 // Wave w keeps resident rows bp*8 + 2w, 2w + 1 and holds two travellers from
-// block bq, which move one wave along per step through LDS (4 steps); each
-// step is two sub-steps of two disjoint pairs.
+// block bq, which move one wave along per step through LDS (4 steps) with
+// their squared norms; each step is two sub-steps of two disjoint pairs.
 constexpr int CW = 4;
 
 template <int E>
@@ -520,6 +520,7 @@ __global__ __launch_bounds__(CW * 64, 2) void jacobi_reg_cross_kernel(const JacI
                                                                       int round, int sweep,
                                                                       double eps_scale) {
   extern __shared__ double2 slots[];  // CW slots of two travellers (2 x 64 E elements)
+  __shared__ double s_tn[CW][2];      // the travellers' squared norms
   __shared__ int s_rot;
   RegCtx c;
   if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
@@ -536,19 +537,27 @@ __global__ __launch_bounds__(CW * 64, 2) void jacobi_reg_cross_kernel(const JacI
     rv_load<E>(t0, c.it.w + (size_t)min(h0, n - 1) * m, h0 < n, m, lane);
     rv_load<E>(t1, c.it.w + (size_t)min(h1, n - 1) * m, h1 < n, m, lane);
   }
+  double nr0 = rv_norm2<E>(r0), nr1 = rv_norm2<E>(r1), nt0 = rv_norm2<E>(t0), nt1 = rv_norm2<E>(t1);
   const bool x_is_i = c.bp < c.bq;
   int rot = 0;
   for (int st = 0; st < CW; ++st) {
-    rot += rot2<E>(r0, t0, r1, t1, x_is_i, c.eps, c.floor, lane);
-    rot += rot2<E>(r0, t1, r1, t0, x_is_i, c.eps, c.floor, lane);
+    rot += rot2n<E>(r0, t0, nr0, nt0, r1, t1, nr1, nt1, x_is_i, c.eps, c.floor, lane);
+    rot += rot2n<E>(r0, t1, nr0, nt1, r1, t0, nr1, nt0, x_is_i, c.eps, c.floor, lane);
     if (st == CW - 1) break;
     double2* mine = slots + (size_t)wv * 2 * 64 * E;
     rv_to_lds<E>(t0, mine, lane);
     rv_to_lds<E>(t1, mine + 64 * E, lane);
+    if (lane == 0) {
+      s_tn[wv][0] = nt0;
+      s_tn[wv][1] = nt1;
+    }
     __syncthreads();
-    const double2* prev = slots + (size_t)((wv + CW - 1) % CW) * 2 * 64 * E;
+    const int from = (wv + CW - 1) % CW;
+    const double2* prev = slots + (size_t)from * 2 * 64 * E;
     rv_from_lds<E>(t0, prev, lane);
     rv_from_lds<E>(t1, prev + 64 * E, lane);
+    nt0 = s_tn[from][0];
+    nt1 = s_tn[from][1];
     src = (src + CW - 1) % CW;
     __syncthreads();
   }
