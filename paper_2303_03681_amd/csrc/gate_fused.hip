@@ -86,120 +86,151 @@ __device__ __forceinline__ double rs_pick(const double (&v)[2 * H], int j, bool 
 }
 
 template <int E, class P, int I>
-__device__ __forceinline__ void partials_one(double2 (&T)[FB][E], double2 (&B)[FB][E], double (&v)[32]) {
+__device__ __forceinline__ void partials_one(double2 (&T)[FB][E], double2 (&B)[FB][E], double (&v)[16]) {
   double2 (&X)[FB][E] = blk<E, P::xa(I)>(T, B);
   double2 (&Y)[FB][E] = blk<E, P::ya(I)>(T, B);
-  double acc[4];
-  pair_partials<E>(X[P::xr(I)], Y[P::yr(I)], acc);
-  v[I] = acc[0];
-  v[8 + I] = acc[1];
-  v[16 + I] = acc[2];
-  v[24 + I] = acc[3];
+  pair_partials_xy<E>(X[P::xr(I)], Y[P::yr(I)], v[I], v[8 + I]);
+}
+
+// Tracked squared norms live in LDS, 16 per wave (wn[0..7] top rows,
+// wn[8..15] bottom rows): index of row r of block A.
+template <int A>
+constexpr int nidx(int r) { return A * FB + r; }
+
+// This lane's pair (lane & 7) picks its two tracked norms.
+template <class P, int I>
+__device__ __forceinline__ void pick_idx(int li, int& ix, int& iy) {
+  if (li == I) {
+    ix = nidx<P::xa(I)>(P::xr(I));
+    iy = nidx<P::ya(I)>(P::yr(I));
+  }
 }
 
 template <int E, class P, int I>
-__device__ __forceinline__ int apply_one(double2 (&T)[FB][E], double2 (&B)[FB][E], uint64_t act,
-                                         const Rot& mine) {
-  // lane holding pair I after the reduce-scatter: bits (b1 b0 b4) = I, b2 = b3 = 0
-  constexpr int L = (((I >> 2) & 1) << 1) | ((I >> 1) & 1) | ((I & 1) << 4);
-  if (!((act >> L) & 1)) return 0;
+__device__ __forceinline__ int apply_one(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn, int lane,
+                                         uint64_t act, const Rot& mine, double dn, bool x_is_i) {
+  // pair I is held (real part) by lane I after the reduce-scatter
+  if (!((act >> I) & 1)) return 0;
   Rot rt;
-  rt.c = readlane_d(mine.c, L);
-  rt.ar = readlane_d(mine.ar, L);
-  rt.ai = readlane_d(mine.ai, L);
-  rt.br = readlane_d(mine.br, L);
-  rt.bi = readlane_d(mine.bi, L);
+  rt.c = readlane_d(mine.c, I);
+  rt.ar = readlane_d(mine.ar, I);
+  rt.ai = readlane_d(mine.ai, I);
+  rt.br = readlane_d(mine.br, I);
+  rt.bi = readlane_d(mine.bi, I);
+  const double d = readlane_d(dn, I);
   double2 (&X)[FB][E] = blk<E, P::xa(I)>(T, B);
   double2 (&Y)[FB][E] = blk<E, P::ya(I)>(T, B);
   pair_apply<E>(X[P::xr(I)], Y[P::yr(I)], rt);
+  if (lane == 0) {
+    wn[nidx<P::xa(I)>(P::xr(I))] += x_is_i ? d : -d;
+    wn[nidx<P::ya(I)>(P::yr(I))] -= x_is_i ? d : -d;
+  }
   return 1;
 }
 
+// Eight disjoint pairs with tracked squared norms: the 16 partial sums of
+// x^+y are reduce-scattered (lane bits 3, 2, 1, 0 by DPP, then full sums over
+// bits 4 and 5), so lane l holds component (l >> 3) & 1 (Re, Im) of pair
+// l & 7; the other component comes by a swizzle and every lane computes the
+// rotation of its pair (eight at once).
 template <int E, class P, int... I>
-__device__ __forceinline__ int rot8_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], bool x_is_i,
-                                         double eps, double floor, int lane,
+__device__ __forceinline__ int rot8_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn,
+                                         bool x_is_i, double eps, double floor, int lane,
                                          std::integer_sequence<int, I...>) {
-  double v[32];  // v[8c + i]: component c of pair i
+  double v[16];  // v[8c + i]: component c (0 Re, 1 Im) of x_i^+ y_i
   (partials_one<E, P, I>(T, B, v), ...);
-  // reduce-scatter: lane bits 3, 2, 1, 0 by DPP, then 4; value index bits
-  // (4, 3, 2, 1, 0) <- lane bits (3, 2, 1, 0, 4)
-  double v16[16], v8[8], v4[4], v2[2];
+  double v8[8], v4[4], v2[2];
   {
     const bool hi = (lane >> 3) & 1;
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      v16[j] = rs_pick<16>(v, j, hi, false) + dpp_mov<0x140>(rs_pick<16>(v, j, hi, true));
+    for (int j = 0; j < 8; ++j)
+      v8[j] = rs_pick<8>(v, j, hi, false) + dpp_mov<0x140>(rs_pick<8>(v, j, hi, true));
   }
   {
     const bool hi = (lane >> 2) & 1;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      v8[j] = rs_pick<8>(v16, j, hi, false) + dpp_mov<0x141>(rs_pick<8>(v16, j, hi, true));
+    for (int j = 0; j < 4; ++j)
+      v4[j] = rs_pick<4>(v8, j, hi, false) + dpp_mov<0x141>(rs_pick<4>(v8, j, hi, true));
   }
   {
     const bool hi = (lane >> 1) & 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      v4[j] = rs_pick<4>(v8, j, hi, false) + dpp_mov<0x4E>(rs_pick<4>(v8, j, hi, true));
-  }
-  {
-    const bool hi = lane & 1;
-#pragma unroll
     for (int j = 0; j < 2; ++j)
-      v2[j] = rs_pick<2>(v4, j, hi, false) + dpp_mov<0xB1>(rs_pick<2>(v4, j, hi, true));
+      v2[j] = rs_pick<2>(v4, j, hi, false) + dpp_mov<0x4E>(rs_pick<2>(v4, j, hi, true));
   }
   double x;
   {
-    const bool hi = (lane >> 4) & 1;
-    x = rs_pick<1>(v2, 0, hi, false) + swizzle<swz(16)>(rs_pick<1>(v2, 0, hi, true));
+    const bool hi = lane & 1;
+    x = rs_pick<1>(v2, 0, hi, false) + dpp_mov<0xB1>(rs_pick<1>(v2, 0, hi, true));
   }
-  x += __shfl_xor(x, 32, 64);  // the same bits in lanes l and l ^ 32
-  // gather the four components c = (lane bit 3, lane bit 2) of this lane's pair
-  const double x4 = swizzle<swz(4)>(x);
-  const double x8 = swizzle<swz(8)>(x);
-  const double x12 = swizzle<swz(12)>(x);
-  const int c = ((lane >> 2) & 3);
-  const double cc0 = c == 0 ? x : c == 1 ? x4 : c == 2 ? x8 : x12;
-  const double cc1 = c == 1 ? x : c == 0 ? x4 : c == 3 ? x8 : x12;
-  const double cc2 = c == 2 ? x : c == 3 ? x4 : c == 0 ? x8 : x12;
-  const double cc3 = c == 3 ? x : c == 2 ? x4 : c == 1 ? x8 : x12;
-  const double acc[4] = {cc0, cc1, cc2, cc3};
+  x += swizzle<swz(16)>(x);
+  x += __shfl_xor(x, 32, 64);  // the same bits in every lane that holds this sum
+  const double other = swizzle<swz(8)>(x);
+  const bool im_lane = (lane >> 3) & 1;
+  const int li = lane & 7;
+  int ix = 0, iy = 0;
+  (pick_idx<P, I>(li, ix, iy), ...);
   Rot mine{1.0, 0.0, 0.0, 0.0, 0.0};
-  const bool a = pair_rot_lane(acc, x_is_i, eps, floor, mine);
+  double dn = 0.0;
+  const bool a = pair_rot_core(wn[ix], wn[iy], im_lane ? other : x, im_lane ? x : other, x_is_i, eps,
+                               floor, mine, &dn);
   const uint64_t act = __ballot(a);
   if (act == 0) return 0;
-  return (apply_one<E, P, I>(T, B, act, mine) + ...);
+  return (apply_one<E, P, I>(T, B, wn, lane, act, mine, dn, x_is_i) + ...);
 }
 
 template <int E, class P>
-__device__ __forceinline__ int rot8(double2 (&T)[FB][E], double2 (&B)[FB][E], bool x_is_i,
+__device__ __forceinline__ int rot8(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn, bool x_is_i,
                                     double eps, double floor, int lane) {
-  return rot8_impl<E, P>(T, B, x_is_i, eps, floor, lane, std::make_integer_sequence<int, 8>{});
+  return rot8_impl<E, P>(T, B, wn, x_is_i, eps, floor, lane, std::make_integer_sequence<int, 8>{});
 }
 
 template <int E, int... S>
-__device__ __forceinline__ int cross_all_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], bool top_is_i,
+__device__ __forceinline__ int cross_all_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn,
+                                              bool top_is_i, double eps, double floor, int lane,
+                                              std::integer_sequence<int, S...>) {
+  return (rot8<E, CrossPairs<S>>(T, B, wn, top_is_i, eps, floor, lane) + ...);
+}
+
+template <int E, int... S>
+__device__ __forceinline__ int intra_all_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn,
                                               double eps, double floor, int lane,
                                               std::integer_sequence<int, S...>) {
-  return (rot8<E, CrossPairs<S>>(T, B, top_is_i, eps, floor, lane) + ...);
-}
-
-template <int E, int... S>
-__device__ __forceinline__ int intra_all_impl(double2 (&T)[FB][E], double2 (&B)[FB][E], double eps,
-                                              double floor, int lane, std::integer_sequence<int, S...>) {
-  return (rot8<E, IntraPairs<S>>(T, B, true, eps, floor, lane) + ...);
+  return (rot8<E, IntraPairs<S>>(T, B, wn, true, eps, floor, lane) + ...);
 }
 
 template <int E>
-__device__ __forceinline__ int cross_all(double2 (&T)[FB][E], double2 (&B)[FB][E], bool top_is_i,
+__device__ __forceinline__ int cross_all(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn,
+                                         bool top_is_i, double eps, double floor, int lane) {
+  return cross_all_impl<E>(T, B, wn, top_is_i, eps, floor, lane, std::make_integer_sequence<int, 8>{});
+}
+
+template <int E>
+__device__ __forceinline__ int intra_all(double2 (&T)[FB][E], double2 (&B)[FB][E], double* wn,
                                          double eps, double floor, int lane) {
-  return cross_all_impl<E>(T, B, top_is_i, eps, floor, lane, std::make_integer_sequence<int, 8>{});
+  return intra_all_impl<E>(T, B, wn, eps, floor, lane, std::make_integer_sequence<int, 7>{});
 }
 
+// Fresh squared norms of the 16 rows a wave holds, into the wave's LDS row wn.
 template <int E>
-__device__ __forceinline__ int intra_all(double2 (&T)[FB][E], double2 (&B)[FB][E], double eps,
-                                         double floor, int lane) {
-  return intra_all_impl<E>(T, B, eps, floor, lane, std::make_integer_sequence<int, 7>{});
+__device__ __forceinline__ void row_norms(const double2 (&T)[FB][E], const double2 (&B)[FB][E],
+                                          double* wn, int lane) {
+  double v[2 * FB];
+#pragma unroll
+  for (int t = 0; t < FB; ++t) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      a += T[t][k].x * T[t][k].x + T[t][k].y * T[t][k].y;
+      b += B[t][k].x * B[t][k].x + B[t][k].y * B[t][k].y;
+    }
+    v[t] = a;
+    v[FB + t] = b;
+  }
+  wave_sum_n<2 * FB>(v);
+#pragma unroll
+  for (int t = 0; t < 2 * FB; ++t)
+    if (lane == t) wn[t] = v[t];
 }
 
 template <int E>
@@ -248,20 +279,24 @@ __device__ __forceinline__ void advance(double2 (&T)[FB][E], double2 (&B)[FB][E]
 // the caller: wave w holds blocks w and nb-1-w): sweeps until one makes no
 // rotation.  Returns the sweeps used, or 0 if max_sweeps were not enough.
 // The block arrangement is the initial one again on return.  s_rot: two ints
-// of shared memory, zero on entry.  Every thread of the workgroup calls this.
+// of shared memory, zero on entry; norms: FW x 16 doubles of shared memory.
+// Every thread of the workgroup calls this.
 template <int E>
 __device__ __forceinline__ int jacobi_sweeps(double2 (&T)[FB][E], double2 (&B)[FB][E], double2* xs,
-                                             int* s_rot, int nb, int max_sweeps, double eps,
-                                             double floor) {
+                                             int* s_rot, double* norms, int nb, int max_sweeps,
+                                             double eps, double floor) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double* wn = norms + wv * 2 * FB;
   const int nwa = nb / 2;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     int rot = 0;
     for (int r = 0; r < nb - 1; ++r) {
       if (wv < nwa) {
-        if (r == 0) rot += intra_all<E>(T, B, eps, floor, lane);
+        // squared norms, fresh for every round and then tracked through its rotations
+        row_norms<E>(T, B, wn, lane);
+        if (r == 0) rot += intra_all<E>(T, B, wn, eps, floor, lane);
         const bool top_is_i = pos_id(wv, r, nb) < pos_id(nb - 1 - wv, r, nb);
-        rot += cross_all<E>(T, B, top_is_i, eps, floor, lane);
+        rot += cross_all<E>(T, B, wn, top_is_i, eps, floor, lane);
       }
       if (nb > 2) advance<E>(T, B, xs, wv, nwa, lane);
     }
@@ -285,6 +320,7 @@ __device__ __forceinline__ void set_status(const FusedGate& g, int code) {
 
 // Workgroup-shared scalars of one gate.
 struct FusedShared {
+  double norms[FW * 2 * FB];  // tracked squared row norms of the Jacobi sweeps
   double sig[FMAXN];
   int perm[FMAXN];
   int rank[FMAXN];
@@ -399,7 +435,7 @@ __device__ __forceinline__ void gate_body(const FusedGate& g, double2* xs, Fused
   const double floor = eps * eps * fro2;
 
   // ---- Algorithm 1
-  const int done = jacobi_sweeps<E>(T, B, xs, s_rot, nb, g.max_sweeps, eps, floor);
+  const int done = jacobi_sweeps<E>(T, B, xs, s_rot, sh.norms, nb, g.max_sweeps, eps, floor);
   if (!done) {
     if (threadIdx.x == 0) set_status(g, 2);
     return;
@@ -608,7 +644,7 @@ __global__ void gate1q_dev_kernel(double2* b, const double2* u, const int* dims,
 // from *it.fro2.
 template <int E>
 __device__ __forceinline__ void jacobi_small_body(const JacItem& it, int max_sweeps, double eps_scale,
-                                                  double2* xs, int* s_rot) {
+                                                  double2* xs, int* s_rot, double* norms) {
   const int n = it.n, m = it.m;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int nb = (n + FB - 1) / FB;
@@ -626,7 +662,7 @@ __device__ __forceinline__ void jacobi_small_body(const JacItem& it, int max_swe
     }
   const double eps = eps_scale * (double)m;
   const double floor = eps * eps * (*it.fro2);
-  const int done = jacobi_sweeps<E>(T, B, xs, s_rot, nb, max_sweeps, eps, floor);
+  const int done = jacobi_sweeps<E>(T, B, xs, s_rot, norms, nb, max_sweeps, eps, floor);
   if (wv < nwa) {
 #pragma unroll
     for (int t = 0; t < FB; ++t)
@@ -646,14 +682,15 @@ __global__ __launch_bounds__(FW * 64) void jacobi_small_kernel(const JacItem* it
                                                                double eps_scale) {
   extern __shared__ double2 xs[];
   __shared__ int s_rot[2];
+  __shared__ double norms[FW * 2 * FB];
   const JacItem it = items[blockIdx.x];
   if (threadIdx.x == 0) {
     s_rot[0] = 0;
     s_rot[1] = 0;
   }
   __syncthreads();
-  if (it.m <= 64) jacobi_small_body<1>(it, max_sweeps, eps_scale, xs, s_rot);
-  else jacobi_small_body<2>(it, max_sweeps, eps_scale, xs, s_rot);
+  if (it.m <= 64) jacobi_small_body<1>(it, max_sweeps, eps_scale, xs, s_rot, norms);
+  else jacobi_small_body<2>(it, max_sweeps, eps_scale, xs, s_rot, norms);
 }
 
 size_t fused_lds_bytes() {
