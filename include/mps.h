@@ -234,6 +234,9 @@ typedef struct {
   double gates_ms;          /* wall time of gate application                   */
   double canon_ms;          /* wall time of canonicalisation                   */
   int64_t jacobi_sweeps;    /* total Jacobi sweeps executed                    */
+  double jacobi_ms;         /* device time of the multi-launch Jacobi rounds   */
+  double jacobi_flops;      /* their algorithmic FLOPs: 32m per rotated pair,   *
+                             * 8m per pair visited without rotation (rows of m) */
 } mps_timing;
 
 mps_status mps_set_timing(mps_handle h, int32_t enabled); /* also resets counters */

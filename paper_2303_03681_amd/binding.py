@@ -59,6 +59,8 @@ class Timing(C.Structure):
         ("gates_ms", C.c_double),
         ("canon_ms", C.c_double),
         ("jacobi_sweeps", C.c_int64),
+        ("jacobi_ms", C.c_double),
+        ("jacobi_flops", C.c_double),
     ]
 
     def as_dict(self):

@@ -170,12 +170,13 @@ __device__ __forceinline__ int rot8_impl(double2 (&T)[FB][E], double2 (&B)[FB][E
   const int li = lane & 7;
   int ix = 0, iy = 0;
   (pick_idx<P, I>(li, ix, iy), ...);
+  const double bxx = wn[ix], byy = wn[iy];
+  const double br = im_lane ? other : x, bi = im_lane ? x : other;
+  const uint64_t act = __ballot(pair_needs_rot(bxx, byy, br, bi, eps, floor)) & 0xFFull;
+  if (act == 0) return 0;  // no pair rotates: skip the rotation formula
   Rot mine{1.0, 0.0, 0.0, 0.0, 0.0};
   double dn = 0.0;
-  const bool a = pair_rot_core(wn[ix], wn[iy], im_lane ? other : x, im_lane ? x : other, x_is_i, eps,
-                               floor, mine, &dn);
-  const uint64_t act = __ballot(a);
-  if (act == 0) return 0;
+  pair_rot_coeffs(bxx, byy, br, bi, x_is_i, mine, &dn);
   return (apply_one<E, P, I>(T, B, wn, lane, act, mine, dn, x_is_i) + ...);
 }
 

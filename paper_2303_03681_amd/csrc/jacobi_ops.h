@@ -37,12 +37,19 @@ struct Rot {
 // when the pair is already orthogonal to the tolerance (|b_ij| <= eps
 // sqrt(b_ii b_jj) or <= floor).  *dn receives t |b_ij|, by which b_ii grows
 // and b_jj shrinks under the rotation.
-__device__ __forceinline__ bool pair_rot_core(double bxx, double byy, double br, double bi, bool x_is_i,
-                                              double eps, double floor, Rot& rt, double* dn) {
-  const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
-  // |b_ij| > floor and |b_ij| > eps sqrt(b_ii b_jj), compared in squares
+// Algorithm 1's rotation test: |b_ij| > floor and |b_ij| > eps sqrt(b_ii
+// b_jj), compared in squares (symmetric in the two rows).
+__device__ __forceinline__ bool pair_needs_rot(double bxx, double byy, double br, double bi, double eps,
+                                               double floor) {
   const double mag2 = br * br + bi * bi;
-  if (!(mag2 > floor * floor) || !(mag2 > eps * eps * (bii * bjj))) return false;
+  return mag2 > floor * floor && mag2 > eps * eps * (bxx * byy);
+}
+
+// The rotation itself, for a pair that passed pair_needs_rot.
+__device__ __forceinline__ void pair_rot_coeffs(double bxx, double byy, double br, double bi, bool x_is_i,
+                                                Rot& rt, double* dn) {
+  const double bii = x_is_i ? bxx : byy, bjj = x_is_i ? byy : bxx;
+  const double mag2 = br * br + bi * bi;
   const double rinv = rsqrt(mag2);  // 1 / |b_ij|
   const double tau = (bii - bjj) * (0.5 * rinv);
   const double at = fabs(tau);
@@ -59,6 +66,12 @@ __device__ __forceinline__ bool pair_rot_core(double bxx, double byy, double br,
   rt.br = x_is_i ? qr : pr;
   rt.bi = x_is_i ? qi : pi;
   if (dn) *dn = t * (mag2 * rinv);
+}
+
+__device__ __forceinline__ bool pair_rot_core(double bxx, double byy, double br, double bi, bool x_is_i,
+                                              double eps, double floor, Rot& rt, double* dn) {
+  if (!pair_needs_rot(bxx, byy, br, bi, eps, floor)) return false;
+  pair_rot_coeffs(bxx, byy, br, bi, x_is_i, rt, dn);
   return true;
 }
 

@@ -473,11 +473,13 @@ __device__ __forceinline__ int rot2n(RegVec<E>& x0, RegVec<E>& y0, double& nx0, 
   const double other = swizzle<swz(8)>(x);
   const bool im_lane = (lane >> 3) & 1;
   const bool p1 = (lane >> 2) & 1;
+  const double bxx = p1 ? nx1 : nx0, byy = p1 ? ny1 : ny0;
+  const double br = im_lane ? other : x, bi = im_lane ? x : other;
+  const uint64_t act = __ballot(pair_needs_rot(bxx, byy, br, bi, eps, floor));
+  if (!(act & 17ull)) return 0;  // neither pair rotates: skip the rotation formula
   Rot mine{1.0, 0.0, 0.0, 0.0, 0.0};
   double dn = 0.0;
-  const bool a = pair_rot_core(p1 ? nx1 : nx0, p1 ? ny1 : ny0, im_lane ? other : x, im_lane ? x : other,
-                               x_is_i, eps, floor, mine, &dn);
-  const uint64_t act = __ballot(a);
+  pair_rot_coeffs(bxx, byy, br, bi, x_is_i, mine, &dn);
   int rot = 0;
   // pair i is held (Re component) by lane 4 i
   if (act & 1ull) {

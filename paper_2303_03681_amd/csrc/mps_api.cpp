@@ -171,6 +171,7 @@ struct mps_state {
   bool timing = false;
   std::vector<hipEvent_t> ev_env, ev_close;
   size_t ev_env_used = 0, ev_close_used = 0;
+  hipEvent_t ev_jac[2] = {nullptr, nullptr};
   mps_timing tm{};
 
   double2* cur(int q) { return site[site_cur[q]][q]; }
@@ -408,6 +409,12 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   for (const JacItem& b : jp.reg) is_multi[b.rot - all[0].rot] = 1;
   for (const JacItem& b : jp.block) is_multi[b.rot - all[0].rot] = 1;
   const int nmulti = (int)(jp.reg.size() + jp.block.size());
+  const bool timed = h->timing && nmulti > 0;
+  if (timed) {
+    for (hipEvent_t& ev : h->ev_jac)
+      if (!ev) HIP_TRY(h, hipEventCreate(&ev));
+    HIP_TRY(h, hipEventRecord(h->ev_jac[0], h->stream));  // after the one-launch items
+  }
   if (nmulti > 0) {
     std::vector<int> rot(count);
     int done = 0;
@@ -430,6 +437,7 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
           if (is_multi[i] && rot[i] == 0) ++done;
       }
     }
+    if (timed) HIP_TRY(h, hipEventRecord(h->ev_jac[1], h->stream));
     // exact first rotation-free sweep of every multi-launch item
     std::vector<int> hist((size_t)h->max_sweeps * count);
     HIP_TRY(h, hipMemcpyAsync(hist.data(), all[0].rot, sizeof(int) * hist.size(),
@@ -442,6 +450,20 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
             first_zero[i] = sw + 1;
             break;
           }
+    if (timed) {
+      float ms = 0.f;
+      HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_jac[0], h->ev_jac[1]));
+      h->tm.jacobi_ms += ms;
+      for (int i = 0; i < count; ++i) {
+        if (!is_multi[i]) continue;
+        const double pairs = 0.5 * (double)all[i].n * (all[i].n - 1), m = all[i].m;
+        const int sweeps = first_zero[i] > 0 ? first_zero[i] : h->max_sweeps;
+        for (int sw = 0; sw < sweeps; ++sw) {
+          const double r = hist[(size_t)sw * count + i];
+          h->tm.jacobi_flops += r * 32.0 * m + (pairs - r) * 8.0 * m;
+        }
+      }
+    }
   }
   // one-launch items report their sweeps themselves
   std::vector<JacItem> one(jp.small);
@@ -1222,6 +1244,8 @@ mps_status mps_destroy(mps_handle h) {
   for (auto& a : h->allocs) (void)hipFree(a.first);
   for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_close) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_jac)
+    if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return MPS_OK;
