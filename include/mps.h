@@ -188,7 +188,12 @@ mps_status mps_pauli_sum_export(mps_pauli_sum p, int32_t* left_parent, int32_t* 
 
 /* E = sum_k c_k Re<P_k> (Methods, UCC: the energy from the expectation
  * values of the qubit Hamiltonian; Eqs. expec1/expec2 for each <P_k>).
- * Canonicalises first if a gate was applied since the last
+ * If a gate was applied since the state was last brought to canonical
+ * form, a right-to-left SVD sweep (the second half of mps_canonicalize)
+ * first makes every site right-orthonormal and the norm 1, and the left
+ * environments start from the identity-prefix products sum B^+ L B (FP64)
+ * instead of diag(lambda^2), which needs the Schmidt values of the full
+ * canonical form; the lambdas are exact Schmidt values again only after
  * mps_canonicalize.  The transfer-matrix products run in `prec`; the
  * per-string values are summed in FP64 with compensation in string order, so
  * the result does not depend on how strings are batched.  per_term, if not

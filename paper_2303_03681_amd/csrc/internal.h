@@ -198,6 +198,7 @@ hipError_t launch_env_gemm2_split(const EnvChild<float2>* items, int count, cons
 
 hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr, int dl, int dr,
                                int elem_bytes, hipStream_t s);
+hipError_t launch_root_copy(const double2* src, void* dst, size_t count, int elem_bytes, hipStream_t s);
 hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,
                         hipStream_t s);
 hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles,

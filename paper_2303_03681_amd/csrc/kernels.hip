@@ -1119,6 +1119,28 @@ hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int 
   return hipGetLastError();
 }
 
+// FP64 environment -> a root slot in the environment precision.
+template <typename C2>
+__global__ void root_copy_kernel(const double2* src, C2* dst, size_t count) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) {
+    C2 v;
+    v.x = src[i].x;
+    v.y = src[i].y;
+    dst[i] = v;
+  }
+}
+
+hipError_t launch_root_copy(const double2* src, void* dst, size_t count, int elem_bytes, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const int blocks = cdiv((long long)count, 256);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(root_copy_kernel<double2>, dim3(blocks), dim3(256), 0, s, src, (double2*)dst, count);
+  else
+    hipLaunchKernelGGL(root_copy_kernel<float2>, dim3(blocks), dim3(256), 0, s, src, (float2*)dst, count);
+  return hipGetLastError();
+}
+
 // Closing traces: Tr(L_a R_b) = sum_{xy} L_a[x][y] R_b[y][x] = sum_x L_a[x] R^T_b[x]
 // with right environments stored transposed; computed in FP64, real part
 // only, for the 64x64 tiles of (prefix, suffix) pairs that some string needs.

@@ -129,7 +129,14 @@ struct mps_state {
   std::vector<size_t> site_cap;  // complex elements
   std::vector<double*> lam[2];
   std::vector<int> lam_cur;
-  bool canonical = true;
+  bool canonical = true;        // exact canonical form: right-orthonormal sites, Schmidt lambdas
+  bool right_canonical = true;  // right-orthonormal sites (lambdas not necessarily Schmidt values)
+  // identity-prefix environments L_b = sum over sites < b of B^+ L B (FP64), the
+  // left roots when only right-canonical form is at hand
+  double2* d_chain = nullptr;
+  double2* d_chainx = nullptr;
+  void* d_chaindesc = nullptr;
+  std::vector<size_t> chain_off;
   double norm = 1.0;
   double discarded = 0.0;
   // device helpers
@@ -571,13 +578,16 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
     h->discarded += disc[b];
   }
   h->canonical = false;
+  h->right_canonical = false;
   return MPS_OK;
 }
 
 // ----------------------------------------------------------------------------
 // canonical form: left-to-right orthonormalisation, right-to-left SVD sweep
 
-mps_status canonicalize_impl(mps_state* h) {
+// full: both sweeps (exact canonical form and Schmidt lambdas); otherwise the
+// right-to-left sweep only (right-orthonormal sites, unit norm).
+mps_status canonicalize_impl(mps_state* h, bool full = true) {
   const double t0 = now_ms();
   mps_status st = ensure_ws(h, 1);
   if (st != MPS_OK) return st;
@@ -586,6 +596,7 @@ mps_status canonicalize_impl(mps_state* h) {
   double2* T = h->d_carry[0];
   double2* Tn = h->d_carry[1];
   if ((st = upload(h, T, &one, sizeof(double2))) != MPS_OK) return st;
+  if ((st = ensure_desc(h, 4096)) != MPS_OK) return st;  // descriptors of both sweeps
   double2* W0 = h->ws_c;
   double2* W = h->ws_w;
   char* d = nullptr;
@@ -593,14 +604,13 @@ mps_status canonicalize_impl(mps_state* h) {
   int r = 1;  // rows of the carry
   // ---- left to right: M = T B_q (2r x Db); U of its SVD becomes A_q, carry U^+ M
   const std::vector<int> od = h->dims;  // shapes of the B tensors before the sweep
-  for (int q = 0; q < n; ++q) {
+  for (int q = 0; q < (full ? n : 0); ++q) {
     const int dg = od[q], db = od[q + 1];
     const int m = 2 * r;
     if ((size_t)db * m > h->ws_stride) return fail(MPS_ERR_STATE, "internal: canon workspace");
     CanonLeftItem cl[2] = {{h->cur(q), T, W0, r, dg, db, 0}, {h->cur(q), T, W0, r, dg, db, 1}};
     FinItem fi{W, h->spare(q), nullptr, h->d_k, h->d_scale, h->d_disc, h->d_status,
                db, m, h->cap[q + 1], kCanonCutoff, FIN_LEFT};
-    if ((st = ensure_desc(h, 4096)) != MPS_OK) return st;
     d = (char*)h->d_desc;
     if ((st = upload(h, d, cl, sizeof(cl))) != MPS_OK) return st;
     if ((st = upload(h, d + 512, &fi, sizeof(fi))) != MPS_OK) return st;
@@ -670,8 +680,63 @@ mps_status canonicalize_impl(mps_state* h) {
     rr = k;
   }
   if ((st = sync(h)) != MPS_OK) return st;
-  h->canonical = true;
+  h->canonical = full;
+  h->right_canonical = true;
   h->tm.canon_ms += now_ms() - t0;
+  return MPS_OK;
+}
+
+// Identity-prefix environments (Eq. expec2 with identity letters from the
+// left boundary): L_0 = [1], L_{b+1} = sum_s B_b^{s+} L_b B_b^s, FP64, for
+// b < upto.  Slots and descriptors are laid out once by bond capacity.
+mps_status prefix_chain(mps_state* h, int upto) {
+  const int n = h->n;
+  mps_status st;
+  if (!h->d_chain) {
+    h->chain_off.assign(n + 1, 0);
+    size_t tot = 0, xmax = 1;
+    for (int b = 0; b <= n; ++b) {
+      h->chain_off[b] = tot;
+      tot += (size_t)h->cap[b] * h->cap[b];
+      if (b < n) xmax = std::max(xmax, (size_t)h->cap[b] * 2 * h->cap[b + 1]);
+    }
+    double2 *chain = nullptr, *chainx = nullptr;
+    void* desc = nullptr;
+    auto undo = [&]() {
+      dfree(h, chain);
+      dfree(h, chainx);
+      dfree(h, desc);
+    };
+    if ((st = dalloc_t(h, &chain, tot)) != MPS_OK || (st = dalloc_t(h, &chainx, xmax)) != MPS_OK ||
+        (st = dalloc(h, &desc, (sizeof(EnvParent<double2>) + sizeof(EnvChild<double2>)) * n)) != MPS_OK) {
+      undo();
+      return st;
+    }
+    std::vector<EnvParent<double2>> par(n);
+    std::vector<EnvChild<double2>> chi(n);
+    for (int b = 0; b < n; ++b) {
+      par[b] = EnvParent<double2>{chain + h->chain_off[b], chainx};
+      chi[b] = EnvChild<double2>{chainx, chain + h->chain_off[b + 1], 0};
+    }
+    const double2 one = make_double2(1.0, 0.0);
+    hipError_t e = hipMemcpy(desc, par.data(), sizeof(par[0]) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy((char*)desc + sizeof(par[0]) * n, chi.data(), sizeof(chi[0]) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(chain, &one, sizeof(one), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      undo();
+      return dev_fail(h, "prefix environment set-up", e);
+    }
+    h->d_chain = chain;
+    h->d_chainx = chainx;
+    h->d_chaindesc = desc;
+  }
+  const EnvParent<double2>* dpar = (const EnvParent<double2>*)h->d_chaindesc;
+  const EnvChild<double2>* dchi = (const EnvChild<double2>*)((char*)h->d_chaindesc + sizeof(EnvParent<double2>) * n);
+  for (int b = 0; b < upto; ++b) {
+    HIP_TRY(h, launch_env_gemm1_c128(dpar + b, 1, h->cur(b), h->dims[b], h->dims[b + 1], h->stream));
+    HIP_TRY(h, launch_env_gemm2_c128(dchi + b, 1, h->cur(b), h->dims[b], h->dims[b + 1], h->stream));
+  }
   return MPS_OK;
 }
 
@@ -1047,7 +1112,10 @@ mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int pre
 mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
                        double* per_term) {
   mps_status st;
-  if (!h->canonical && (st = canonicalize_impl(h)) != MPS_OK) return st;
+  // Right-orthonormal sites suffice when the left roots are the identity-prefix
+  // environments; with exact canonical form they are diag(lambda^2) (Eq. expec1).
+  const bool prefix = !h->canonical;
+  if (prefix && !h->right_canonical && (st = canonicalize_impl(h, false)) != MPS_OK) return st;
   const double t0 = now_ms();
   if ((st = build_expect(h, ps, prec)) != MPS_OK) return st;
   ExpectSetup& ex = h->ex;
@@ -1056,8 +1124,18 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   for (int q = 0; q < h->n; ++q)
     HIP_TRY(h, launch_site_prepare(h->cur(q), ex.prep[q].fwd, ex.prep[q].tr, ex.prep[q].dl,
                                    ex.prep[q].dr, el, h->stream));
-  for (const auto& r : ex.roots)
-    HIP_TRY(h, launch_roots(h->lcur(r.bond), r.lroot, r.rroot, r.d, el, h->stream));
+  int upto = 0;
+  for (const auto& r : ex.roots) {
+    HIP_TRY(h, launch_roots(h->lcur(r.bond), prefix ? nullptr : r.lroot, r.rroot, r.d, el, h->stream));
+    if (prefix && r.lroot) upto = std::max(upto, r.bond);
+  }
+  // also with upto = 0: the chain's first slot holds L_0 = [1]
+  if (prefix && (st = prefix_chain(h, upto)) != MPS_OK) return st;
+  if (prefix)
+    for (const auto& r : ex.roots)
+      if (r.lroot)
+        HIP_TRY(h, launch_root_copy(h->d_chain + h->chain_off[r.bond], r.lroot, (size_t)r.d * r.d, el,
+                                    h->stream));
   for (const auto& L : ex.left_launches)
     if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
   for (const auto& L : ex.right_launches)
@@ -1273,7 +1351,7 @@ mps_status mps_reset(mps_handle h, const uint8_t* bits) {
   HIP_TRY(h, hipMemcpyAsync(h->d_bits, b.data(), n, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, launch_init_product(h->d_site_ptrs, h->d_lam_ptrs, h->d_bits, n, h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
-  h->canonical = true;
+  h->canonical = h->right_canonical = true;
   h->norm = 1.0;
   h->discarded = 0.0;
   return MPS_OK;
@@ -1342,6 +1420,7 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
         else
           HIP_TRY(h, launch_gate1q(h->cur(q), ug, h->dims[q] * h->dims[q + 1], h->stream));
         h->canonical = false;
+        h->right_canonical = false;
         ++i;
         if (!h->fused_active) done = i;
         continue;
@@ -1363,6 +1442,7 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
           if ((st = fused_launch(h, qs[b], h->d_gates + (size_t)gi[b] * 16, gi[b])) != MPS_OK)
             return finish(st);
         h->canonical = false;
+        h->right_canonical = false;
         i = j;
         continue;
       }
@@ -1470,7 +1550,7 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const 
     if ((st = fused_flush(h, &bad, &code)) != MPS_OK) return st;
     const int64_t done = bad >= 0 ? bad : n_gates[i];
     if (n_done) n_done[i] = done;
-    if (done > 0) h->canonical = false;
+    if (done > 0) h->canonical = h->right_canonical = false;
     h->tm.gates_ms += dt;
     if (bad >= 0 && first == MPS_OK) {
       first = code == 2 ? MPS_ERR_NOCONV : MPS_ERR_NONFINITE;
@@ -1613,7 +1693,7 @@ mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, cons
   HIP_TRY(h, hipMemcpy(h->lcur(q), lambda_left, sizeof(double) * dl, hipMemcpyHostToDevice));
   h->dims[q] = dl;
   h->dims[q + 1] = dr;
-  h->canonical = true;
+  h->canonical = h->right_canonical = true;
   return MPS_OK;
 }
 

@@ -256,6 +256,43 @@ def test_canonicalize_idempotent(gpu_lib):
         assert np.max(np.abs(g - np.eye(g.shape[0]))) < 1e-12
 
 
+def test_expect_right_sweep_matches_full_canonical_form(gpu_lib):
+    """Expectation after gates brings the state only to right-orthonormal form
+    and starts the left environments from identity-prefix products; the
+    values must equal those after the full canonical form (diag(lambda^2)
+    left roots, Eq. expec1), and a later mps_canonicalize still yields the
+    Schmidt values."""
+    from paper_2303_03681_amd import binding
+    n_s = 6
+    n = 2 * n_s
+    h, g = random_integrals(n_s, workload_rng(71, 0))
+    ps = jw_hamiltonian(h, g)
+    plan = binding.PauliSum(ps.codes, ps.coeffs)
+    ang = workload_rng(71, 1).uniform(-np.pi, np.pi, size=(5, n, 2))
+    gates = fuse_gates(brickwork_gates(n, ang), n)
+    a = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, n_s))
+    b = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, n_s))
+    _apply(a, gates)
+    _apply(b, gates)
+    b.canonicalize()
+    for prec, tol in (("c128", 1e-12), ("c64", 2e-5)):
+        ea, pa = a.expect(plan, prec, per_term=True)
+        eb, pb = b.expect(plan, prec, per_term=True)
+        _say(f"  {prec}: right sweep vs full canonical |dE| {abs(ea - eb):.2e}")
+        assert np.max(np.abs(pa - pb)) < tol
+    # right-orthonormal sites after the expectation
+    for q in range(n):
+        B, _ = a.export_site(q)
+        gq = np.einsum("sab,scb->ac", B, B.conj())
+        assert np.max(np.abs(gq - np.eye(gq.shape[0]))) < 1e-12, q
+    assert abs(a.norm() - b.norm()) < 1e-12
+    a.canonicalize()
+    for q in range(n):
+        assert np.max(np.abs(a.export_site(q)[1] - b.export_site(q)[1])) < 1e-12, q
+    e2 = a.expect(plan, "c128")
+    assert abs(e2 - b.expect(plan, "c128")) < 1e-11
+
+
 def _random_u4(rng):
     z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
     q, r = np.linalg.qr(z)

@@ -145,3 +145,32 @@ def test_serving_budget_evicts_and_keeps_results(gpu_lib):
     b = {(r.fid, r.update): r.energy for r in tight.requests}
     for k in a:
         assert abs(a[k] - b[k]) <= 1e-12
+
+
+def test_apply_gates_multi_failure_is_isolated(gpu_lib):
+    """A gate that fails (sweep limit 1) stops only its own list: the other
+    MPSs finish, n_done reports the applied prefix, and the failed MPS holds
+    exactly the gates before its failure."""
+    from paper_2303_03681_amd import binding
+    n = 8
+    lists = [pack_gates(_ladder(n, 3, 400 + i)) for i in range(3)]
+    good = [binding.Mps(n, 16, 1e-14, bits=hf_bits(n, 4)) for _ in range(2)]
+    bad = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, 4), max_jacobi_sweeps=1)
+    with pytest.raises(binding.MpsError) as ex:
+        binding.apply_gates_multi([good[0], bad, good[1]], lists)
+    assert ex.value.name == "MPS_ERR_NOCONV"
+    done = list(ex.value.n_done)
+    assert done[0] == len(lists[0][0]) and done[2] == len(lists[2][0])
+    k = done[1]
+    assert 0 <= k < len(lists[1][0])
+    ref = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, 4))
+    q0, q1, u = lists[1]
+    if k:
+        ref.apply_gates(q0[:k], q1[:k], u[:k])
+    assert list(bad.bond_dims()) == list(ref.bond_dims())
+    plan = binding.PauliSum(np.eye(n, dtype=np.uint8) * 3, np.ones(n))
+    assert abs(bad.expect(plan) - ref.expect(plan)) < 1e-12
+    for g, l in zip(good, (lists[0], lists[2])):
+        a = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, 4))
+        a.apply_gates(*l)
+        assert abs(g.expect(plan) - a.expect(plan)) < 1e-12
