@@ -295,7 +295,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("c64 environments (FP32 MFMA), FP64 gates/SVD/canonical form/closes/sum"
+        "dtype": ("c64 environments (FP32 MFMA), FP64 gates/SVD/boundary environments/norm/closes/sum"
                   if args.prec == "c64" else "c128 (FP64 MFMA) throughout"),
         "data": "synthetic (seeded random-integral JW Hamiltonian, random brickwork angles)",
         "config": {

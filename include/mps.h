@@ -148,8 +148,9 @@ mps_status mps_set_fused_gates(mps_handle h, int32_t enabled);
  * singular values (<= 1e-14 ||sigma||) are dropped. */
 mps_status mps_canonicalize(mps_handle h);
 
-/* Norm ||psi|| found by the last mps_canonicalize (1 for a normalised
- * state). */
+/* Norm ||psi|| found by the last mps_canonicalize (before it normalised the
+ * state) or, after gates, by the last mps_expect_pauli_sum; 1 after
+ * create/reset. */
 mps_status mps_norm(mps_handle h, double* norm);
 
 /* Sum of the relative discarded weights sum_{j>k} sigma_j^2 / sum sigma_j^2
@@ -188,13 +189,14 @@ mps_status mps_pauli_sum_export(mps_pauli_sum p, int32_t* left_parent, int32_t* 
 
 /* E = sum_k c_k Re<P_k> (Methods, UCC: the energy from the expectation
  * values of the qubit Hamiltonian; Eqs. expec1/expec2 for each <P_k>).
- * If a gate was applied since the state was last brought to canonical
- * form, a right-to-left SVD sweep (the second half of mps_canonicalize)
- * first makes every site right-orthonormal and the norm 1, and the left
- * environments start from the identity-prefix products sum B^+ L B (FP64)
- * instead of diag(lambda^2), which needs the Schmidt values of the full
- * canonical form; the lambdas are exact Schmidt values again only after
- * mps_canonicalize.  The transfer-matrix products run in `prec`; the
+ * The state is not modified.  In exact canonical form (after create/reset,
+ * mps_canonicalize or mps_import_site) the tries start from diag(lambda^2)
+ * and the identity (Eqs. expec1, rc).  After gates, whose truncation leaves
+ * the sites only nearly right-orthonormal, they start instead from the
+ * identity environments of both boundaries, sum B^+ L B and sum B R B^+
+ * (FP64, one chain of N updates each), and every <P_k> is divided by
+ * <psi|psi>: the same values, without canonicalisation.  mps_norm then
+ * reports sqrt(<psi|psi>).  The transfer-matrix products run in `prec`; the
  * per-string values are summed in FP64 with compensation in string order, so
  * the result does not depend on how strings are batched.  per_term, if not
  * NULL, receives Re<P_k> for every k (n_terms doubles). */

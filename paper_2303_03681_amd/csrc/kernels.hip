@@ -1194,15 +1194,17 @@ hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int
   return launch_cgemm<64, 64, 16>(p, n_tiles, 64, 64, s);
 }
 
-__global__ void gather_kernel(const double* g, const int64_t* gidx, double* per_term, int64_t n) {
+// <P_k> = closing trace / <psi|psi> (nrm null: unit norm)
+__global__ void gather_kernel(const double* g, const int64_t* gidx, const double2* nrm, double* per_term,
+                              int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (i < n) per_term[i] = g[gidx[i]];
+  if (i < n) per_term[i] = nrm ? g[gidx[i]] / nrm->x : g[gidx[i]];
 }
 
-hipError_t launch_gather(const double* g, const int64_t* gidx, double* per_term, int64_t n,
-                         hipStream_t s) {
+hipError_t launch_gather(const double* g, const int64_t* gidx, const double2* nrm, double* per_term,
+                         int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, gidx,
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, gidx, nrm,
                      per_term, n);
   return hipGetLastError();
 }

@@ -129,12 +129,13 @@ struct mps_state {
   std::vector<size_t> site_cap;  // complex elements
   std::vector<double*> lam[2];
   std::vector<int> lam_cur;
-  bool canonical = true;        // exact canonical form: right-orthonormal sites, Schmidt lambdas
-  bool right_canonical = true;  // right-orthonormal sites (lambdas not necessarily Schmidt values)
-  // identity-prefix environments L_b = sum over sites < b of B^+ L B (FP64), the
-  // left roots when only right-canonical form is at hand
-  double2* d_chain = nullptr;
-  double2* d_chainx = nullptr;
+  bool canonical = true;  // exact canonical form: right-orthonormal sites, Schmidt lambdas
+  // identity environments from both boundaries (FP64), the trie roots when the
+  // sites are not in exact canonical form: left L_b (slot b), right R_b^T
+  double2* d_lchain = nullptr;
+  double2* d_rchain = nullptr;
+  double2* d_chainx = nullptr;  // GEMM1 output of one chain step
+  double2* d_chaintr = nullptr; // one site tensor, transposed, for the right chain
   void* d_chaindesc = nullptr;
   std::vector<size_t> chain_off;
   double norm = 1.0;
@@ -578,16 +579,13 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
     h->discarded += disc[b];
   }
   h->canonical = false;
-  h->right_canonical = false;
   return MPS_OK;
 }
 
 // ----------------------------------------------------------------------------
 // canonical form: left-to-right orthonormalisation, right-to-left SVD sweep
 
-// full: both sweeps (exact canonical form and Schmidt lambdas); otherwise the
-// right-to-left sweep only (right-orthonormal sites, unit norm).
-mps_status canonicalize_impl(mps_state* h, bool full = true) {
+mps_status canonicalize_impl(mps_state* h) {
   const double t0 = now_ms();
   mps_status st = ensure_ws(h, 1);
   if (st != MPS_OK) return st;
@@ -604,7 +602,7 @@ mps_status canonicalize_impl(mps_state* h, bool full = true) {
   int r = 1;  // rows of the carry
   // ---- left to right: M = T B_q (2r x Db); U of its SVD becomes A_q, carry U^+ M
   const std::vector<int> od = h->dims;  // shapes of the B tensors before the sweep
-  for (int q = 0; q < (full ? n : 0); ++q) {
+  for (int q = 0; q < n; ++q) {
     const int dg = od[q], db = od[q + 1];
     const int m = 2 * r;
     if ((size_t)db * m > h->ws_stride) return fail(MPS_ERR_STATE, "internal: canon workspace");
@@ -680,62 +678,86 @@ mps_status canonicalize_impl(mps_state* h, bool full = true) {
     rr = k;
   }
   if ((st = sync(h)) != MPS_OK) return st;
-  h->canonical = full;
-  h->right_canonical = true;
+  h->canonical = true;
   h->tm.canon_ms += now_ms() - t0;
   return MPS_OK;
 }
 
-// Identity-prefix environments (Eq. expec2 with identity letters from the
-// left boundary): L_0 = [1], L_{b+1} = sum_s B_b^{s+} L_b B_b^s, FP64, for
-// b < upto.  Slots and descriptors are laid out once by bond capacity.
-mps_status prefix_chain(mps_state* h, int upto) {
+// Identity environments from both boundaries (Eq. expec2 with identity
+// letters), FP64:  L_0 = [1], L_{b+1} = sum_s B_b^{s+} L_b B_b^s for b < N, so
+// that L_N = <psi|psi>;  R_N = [1] and, in the transposed form of the right
+// pass, R_b^T = sum_s (B_b^{sT})^+ R_{b+1}^T B_b^{sT} for b >= rmin.  They
+// replace diag(lambda^2) and the identity (Eqs. expec1, rc) as trie roots
+// when the sites are not in exact canonical form.  Slots and descriptors are
+// laid out once by bond capacity.
+mps_status identity_chains(mps_state* h, int rmin) {
   const int n = h->n;
   mps_status st;
-  if (!h->d_chain) {
-    h->chain_off.assign(n + 1, 0);
+  using P = EnvParent<double2>;
+  using Ch = EnvChild<double2>;
+  if (!h->d_lchain) {
+    std::vector<size_t> off(n + 1, 0);
     size_t tot = 0, xmax = 1;
     for (int b = 0; b <= n; ++b) {
-      h->chain_off[b] = tot;
+      off[b] = tot;
       tot += (size_t)h->cap[b] * h->cap[b];
       if (b < n) xmax = std::max(xmax, (size_t)h->cap[b] * 2 * h->cap[b + 1]);
     }
-    double2 *chain = nullptr, *chainx = nullptr;
+    double2 *lc = nullptr, *rc = nullptr, *cx = nullptr, *ctr = nullptr;
     void* desc = nullptr;
     auto undo = [&]() {
-      dfree(h, chain);
-      dfree(h, chainx);
+      dfree(h, lc);
+      dfree(h, rc);
+      dfree(h, cx);
+      dfree(h, ctr);
       dfree(h, desc);
     };
-    if ((st = dalloc_t(h, &chain, tot)) != MPS_OK || (st = dalloc_t(h, &chainx, xmax)) != MPS_OK ||
-        (st = dalloc(h, &desc, (sizeof(EnvParent<double2>) + sizeof(EnvChild<double2>)) * n)) != MPS_OK) {
+    if ((st = dalloc_t(h, &lc, tot)) != MPS_OK || (st = dalloc_t(h, &rc, tot)) != MPS_OK ||
+        (st = dalloc_t(h, &cx, xmax)) != MPS_OK || (st = dalloc_t(h, &ctr, xmax)) != MPS_OK ||
+        (st = dalloc(h, &desc, 2 * (sizeof(P) + sizeof(Ch)) * n)) != MPS_OK) {
       undo();
       return st;
     }
-    std::vector<EnvParent<double2>> par(n);
-    std::vector<EnvChild<double2>> chi(n);
-    for (int b = 0; b < n; ++b) {
-      par[b] = EnvParent<double2>{chain + h->chain_off[b], chainx};
-      chi[b] = EnvChild<double2>{chainx, chain + h->chain_off[b + 1], 0};
+    // [left parents | left children | right parents | right children], indexed by site
+    std::vector<char> host(2 * (sizeof(P) + sizeof(Ch)) * n);
+    P* lp = (P*)host.data();
+    Ch* lch = (Ch*)(lp + n);
+    P* rp = (P*)(lch + n);
+    Ch* rch = (Ch*)(rp + n);
+    for (int q = 0; q < n; ++q) {
+      lp[q] = P{lc + off[q], cx};
+      lch[q] = Ch{cx, lc + off[q + 1], 0};
+      rp[q] = P{rc + off[q + 1], cx};
+      rch[q] = Ch{cx, rc + off[q], 0};
     }
     const double2 one = make_double2(1.0, 0.0);
-    hipError_t e = hipMemcpy(desc, par.data(), sizeof(par[0]) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy((char*)desc + sizeof(par[0]) * n, chi.data(), sizeof(chi[0]) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(chain, &one, sizeof(one), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(desc, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(lc, &one, sizeof(one), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(rc + off[n], &one, sizeof(one), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       undo();
-      return dev_fail(h, "prefix environment set-up", e);
+      return dev_fail(h, "identity environment set-up", e);
     }
-    h->d_chain = chain;
-    h->d_chainx = chainx;
+    h->d_lchain = lc;
+    h->d_rchain = rc;
+    h->d_chainx = cx;
+    h->d_chaintr = ctr;
     h->d_chaindesc = desc;
+    h->chain_off = off;
   }
-  const EnvParent<double2>* dpar = (const EnvParent<double2>*)h->d_chaindesc;
-  const EnvChild<double2>* dchi = (const EnvChild<double2>*)((char*)h->d_chaindesc + sizeof(EnvParent<double2>) * n);
-  for (int b = 0; b < upto; ++b) {
-    HIP_TRY(h, launch_env_gemm1_c128(dpar + b, 1, h->cur(b), h->dims[b], h->dims[b + 1], h->stream));
-    HIP_TRY(h, launch_env_gemm2_c128(dchi + b, 1, h->cur(b), h->dims[b], h->dims[b + 1], h->stream));
+  const P* lp = (const P*)h->d_chaindesc;
+  const Ch* lch = (const Ch*)(lp + n);
+  const P* rp = (const P*)(lch + n);
+  const Ch* rch = (const Ch*)(rp + n);
+  for (int q = 0; q < n; ++q) {
+    HIP_TRY(h, launch_env_gemm1_c128(lp + q, 1, h->cur(q), h->dims[q], h->dims[q + 1], h->stream));
+    HIP_TRY(h, launch_env_gemm2_c128(lch + q, 1, h->cur(q), h->dims[q], h->dims[q + 1], h->stream));
+  }
+  for (int q = n - 1; q >= rmin; --q) {
+    HIP_TRY(h, launch_site_prepare(h->cur(q), nullptr, h->d_chaintr, h->dims[q], h->dims[q + 1], 16,
+                                   h->stream));
+    HIP_TRY(h, launch_env_gemm1_c128(rp + q, 1, h->d_chaintr, h->dims[q + 1], h->dims[q], h->stream));
+    HIP_TRY(h, launch_env_gemm2_c128(rch + q, 1, h->d_chaintr, h->dims[q + 1], h->dims[q], h->stream));
   }
   return MPS_OK;
 }
@@ -1112,10 +1134,6 @@ mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int pre
 mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
                        double* per_term) {
   mps_status st;
-  // Right-orthonormal sites suffice when the left roots are the identity-prefix
-  // environments; with exact canonical form they are diag(lambda^2) (Eq. expec1).
-  const bool prefix = !h->canonical;
-  if (prefix && !h->right_canonical && (st = canonicalize_impl(h, false)) != MPS_OK) return st;
   const double t0 = now_ms();
   if ((st = build_expect(h, ps, prec)) != MPS_OK) return st;
   ExpectSetup& ex = h->ex;
@@ -1124,18 +1142,29 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   for (int q = 0; q < h->n; ++q)
     HIP_TRY(h, launch_site_prepare(h->cur(q), ex.prep[q].fwd, ex.prep[q].tr, ex.prep[q].dl,
                                    ex.prep[q].dr, el, h->stream));
-  int upto = 0;
-  for (const auto& r : ex.roots) {
-    HIP_TRY(h, launch_roots(h->lcur(r.bond), prefix ? nullptr : r.lroot, r.rroot, r.d, el, h->stream));
-    if (prefix && r.lroot) upto = std::max(upto, r.bond);
-  }
-  // also with upto = 0: the chain's first slot holds L_0 = [1]
-  if (prefix && (st = prefix_chain(h, upto)) != MPS_OK) return st;
-  if (prefix)
+  // Exact canonical form: diag(lambda^2) and identity roots, unit norm.  After
+  // gates (truncated Hastings updates leave the sites only nearly
+  // right-orthonormal and the norm near 1): identity environments from both
+  // boundaries and division by <psi|psi>, the same values without a sweep.
+  const bool chains = !h->canonical;
+  const double2* nrm = nullptr;
+  if (chains) {
+    int rmin = h->n;
     for (const auto& r : ex.roots)
+      if (r.rroot) rmin = std::min(rmin, r.bond);
+    if ((st = identity_chains(h, rmin)) != MPS_OK) return st;
+    nrm = h->d_lchain + h->chain_off[h->n];
+    for (const auto& r : ex.roots) {
+      const size_t cnt = (size_t)r.d * r.d;
       if (r.lroot)
-        HIP_TRY(h, launch_root_copy(h->d_chain + h->chain_off[r.bond], r.lroot, (size_t)r.d * r.d, el,
-                                    h->stream));
+        HIP_TRY(h, launch_root_copy(h->d_lchain + h->chain_off[r.bond], r.lroot, cnt, el, h->stream));
+      if (r.rroot)
+        HIP_TRY(h, launch_root_copy(h->d_rchain + h->chain_off[r.bond], r.rroot, cnt, el, h->stream));
+    }
+  } else {
+    for (const auto& r : ex.roots)
+      HIP_TRY(h, launch_roots(h->lcur(r.bond), r.lroot, r.rroot, r.d, el, h->stream));
+  }
   for (const auto& L : ex.left_launches)
     if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
   for (const auto& L : ex.right_launches)
@@ -1151,15 +1180,19 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
     h->tm.env_updates += ex.n_updates;
   }
   const int64_t T = ps->plan.n_terms;
-  HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, ex.per_term, T, h->stream));
+  HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, nrm, ex.per_term, T, h->stream));
   HIP_TRY(h, launch_energy(ex.per_term, ex.coeffs, T, ex.energy, h->stream));
   double E = 0.0;
+  double2 nn = make_double2(1.0, 0.0);
   HIP_TRY(h, hipMemcpyAsync(&E, ex.energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (nrm) HIP_TRY(h, hipMemcpyAsync(&nn, nrm, sizeof(double2), hipMemcpyDeviceToHost, h->stream));
   if (per_term && T)
     HIP_TRY(h, hipMemcpyAsync(per_term, ex.per_term, sizeof(double) * T, hipMemcpyDeviceToHost,
                               h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
   if ((st = flush_timing(h)) != MPS_OK) return st;
+  if (!(nn.x > 0.0) || !std::isfinite(nn.x)) return fail(MPS_ERR_NONFINITE, "state norm is zero or not finite");
+  if (nrm) h->norm = std::sqrt(nn.x);
   *energy = E;
   h->tm.expect_ms += now_ms() - t0;
   return MPS_OK;
@@ -1351,7 +1384,7 @@ mps_status mps_reset(mps_handle h, const uint8_t* bits) {
   HIP_TRY(h, hipMemcpyAsync(h->d_bits, b.data(), n, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, launch_init_product(h->d_site_ptrs, h->d_lam_ptrs, h->d_bits, n, h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
-  h->canonical = h->right_canonical = true;
+  h->canonical = true;
   h->norm = 1.0;
   h->discarded = 0.0;
   return MPS_OK;
@@ -1420,7 +1453,6 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
         else
           HIP_TRY(h, launch_gate1q(h->cur(q), ug, h->dims[q] * h->dims[q + 1], h->stream));
         h->canonical = false;
-        h->right_canonical = false;
         ++i;
         if (!h->fused_active) done = i;
         continue;
@@ -1442,7 +1474,6 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
           if ((st = fused_launch(h, qs[b], h->d_gates + (size_t)gi[b] * 16, gi[b])) != MPS_OK)
             return finish(st);
         h->canonical = false;
-        h->right_canonical = false;
         i = j;
         continue;
       }
@@ -1550,7 +1581,7 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const 
     if ((st = fused_flush(h, &bad, &code)) != MPS_OK) return st;
     const int64_t done = bad >= 0 ? bad : n_gates[i];
     if (n_done) n_done[i] = done;
-    if (done > 0) h->canonical = h->right_canonical = false;
+    if (done > 0) h->canonical = false;
     h->tm.gates_ms += dt;
     if (bad >= 0 && first == MPS_OK) {
       first = code == 2 ? MPS_ERR_NOCONV : MPS_ERR_NONFINITE;
@@ -1693,7 +1724,7 @@ mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, cons
   HIP_TRY(h, hipMemcpy(h->lcur(q), lambda_left, sizeof(double) * dl, hipMemcpyHostToDevice));
   h->dims[q] = dl;
   h->dims[q + 1] = dr;
-  h->canonical = h->right_canonical = true;
+  h->canonical = true;
   return MPS_OK;
 }
 

@@ -256,12 +256,11 @@ def test_canonicalize_idempotent(gpu_lib):
         assert np.max(np.abs(g - np.eye(g.shape[0]))) < 1e-12
 
 
-def test_expect_right_sweep_matches_full_canonical_form(gpu_lib):
-    """Expectation after gates brings the state only to right-orthonormal form
-    and starts the left environments from identity-prefix products; the
-    values must equal those after the full canonical form (diag(lambda^2)
-    left roots, Eq. expec1), and a later mps_canonicalize still yields the
-    Schmidt values."""
+def test_expect_without_canonical_form_matches_canonical(gpu_lib):
+    """After gates the expectation starts its tries from the identity
+    environments of both boundaries and divides by <psi|psi>, leaving the
+    state as it is; the values must equal those in exact canonical form
+    (diag(lambda^2) and identity roots, Eqs. expec1, rc)."""
     from paper_2303_03681_amd import binding
     n_s = 6
     n = 2 * n_s
@@ -274,23 +273,39 @@ def test_expect_right_sweep_matches_full_canonical_form(gpu_lib):
     b = binding.Mps(n, 16, 1e-14, bits=hf_bits(n, n_s))
     _apply(a, gates)
     _apply(b, gates)
+    before = [a.export_site(q) for q in range(n)]
     b.canonicalize()
-    for prec, tol in (("c128", 1e-12), ("c64", 2e-5)):
+    for prec, tol in (("c128", 1e-12), ("c64", 2e-5), ("split_f16", 1e-6)):
         ea, pa = a.expect(plan, prec, per_term=True)
         eb, pb = b.expect(plan, prec, per_term=True)
-        _say(f"  {prec}: right sweep vs full canonical |dE| {abs(ea - eb):.2e}")
+        _say(f"  {prec}: identity environments vs canonical form |dE| {abs(ea - eb):.2e}")
         assert np.max(np.abs(pa - pb)) < tol
-    # right-orthonormal sites after the expectation
-    for q in range(n):
-        B, _ = a.export_site(q)
-        gq = np.einsum("sab,scb->ac", B, B.conj())
-        assert np.max(np.abs(gq - np.eye(gq.shape[0]))) < 1e-12, q
+    for q in range(n):  # untouched
+        B, lam = a.export_site(q)
+        assert np.array_equal(B, before[q][0]) and np.array_equal(lam, before[q][1]), q
     assert abs(a.norm() - b.norm()) < 1e-12
     a.canonicalize()
     for q in range(n):
         assert np.max(np.abs(a.export_site(q)[1] - b.export_site(q)[1])) < 1e-12, q
-    e2 = a.expect(plan, "c128")
-    assert abs(e2 - b.expect(plan, "c128")) < 1e-11
+    assert abs(a.expect(plan, "c128") - b.expect(plan, "c128")) < 1e-11
+
+
+def test_expect_of_unnormalised_imported_state(gpu_lib):
+    """A state imported as canonical but scaled by 3 reads <P> unscaled from
+    the identity environments once a gate marks it non-canonical: a one-qubit
+    identity gate changes nothing but the path."""
+    from paper_2303_03681_amd import binding
+    n = 6
+    o = _canonical_random_oracle(n, 8, 9, layers=3)
+    m = binding.Mps(n, 8, 1e-14)
+    for q in range(n):
+        m.import_site(q, 3.0 * o.B[q] if q == 2 else o.B[q], o.lam[q])
+    m.apply_gate(0, -1, np.eye(2))
+    codes = np.random.default_rng(5).integers(0, 4, size=(40, n)).astype(np.uint8)
+    e, per = m.expect(binding.PauliSum(codes, np.ones(40)), "c128", per_term=True)
+    ref = o.expect_terms(codes).real
+    assert np.max(np.abs(per - ref)) < 1e-12
+    assert abs(m.norm() - 3.0) < 1e-12
 
 
 def _random_u4(rng):
