@@ -94,6 +94,10 @@ _SIGS = {
     "mps_jacobi_svd": [_I32, _I32, _P, _P, _P, _P],
     "mps_set_timing": [_P, _I32],
     "mps_set_fused_gates": [_P, _I32],
+    "mps_set_autotune": [_P, _I32],
+    "mps_autotune_table": [_P, _I64, _P],
+    "mps_autotune_reset": [],
+    "mps_set_env_tile": [_P, _I32],
     "mps_apply_gates_multi": [_I32, _P, _P, _P, _P, _P, _P, _P],
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
@@ -282,6 +286,14 @@ class Mps:
         """Allow or forbid the fused single-gate path of apply_gates."""
         _check(_lib.mps_set_fused_gates(self._h, 1 if on else 0))
 
+    def set_autotune(self, on: bool = True):
+        """Choose the environment GEMM tile shapes by measurement (c128, c64)."""
+        _check(_lib.mps_set_autotune(self._h, 1 if on else 0))
+
+    def set_env_tile(self, tile: int = -1):
+        """Force one environment GEMM tile shape (0..5); -1 restores the default."""
+        _check(_lib.mps_set_env_tile(self._h, int(tile)))
+
     def set_timing(self, on: bool = True):
         _check(_lib.mps_set_timing(self._h, 1 if on else 0))
 
@@ -363,3 +375,24 @@ def selftest_mfma() -> np.ndarray:
     out = np.zeros((4, 16, 16), np.float64)
     _check(lib.mps_selftest_mfma(_ptr(out)))
     return out
+
+
+def autotune_table() -> list[dict]:
+    """Tuned launch classes: device, precision, GEMM half, D_l, D_r, item
+    bucket, the chosen tile index and shape, and the time of every tile."""
+    lib = load()
+    n = C.c_int64(0)
+    _check(lib.mps_autotune_table(None, 0, C.byref(n)))
+    buf = C.create_string_buffer(max(n.value, 1))
+    _check(lib.mps_autotune_table(buf, n.value, C.byref(n)))
+    rows = []
+    for line in buf.value.decode().splitlines():
+        f = line.split()
+        rows.append({"device": int(f[0]), "prec": f[1], "half": int(f[2]), "dl": int(f[3]),
+                     "dr": int(f[4]), "bucket": int(f[5]), "tile": int(f[6]), "shape": f[7],
+                     "ms": [float(x) for x in f[8:]]})
+    return rows
+
+
+def autotune_reset():
+    _check(load().mps_autotune_reset())

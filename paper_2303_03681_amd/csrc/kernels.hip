@@ -1022,25 +1022,42 @@ struct EnvG2P {
   }
 };
 
+// One environment GEMM with tile shape kEnvTileShape[tile] (all shapes give
+// bitwise-identical results: every output element accumulates its K range in
+// the same order of 16x16x4 steps whatever the tile).
+template <class P>
+hipError_t launch_env_tile(const P& p, int tile, int count, int m, int n, hipStream_t s) {
+  switch (tile) {
+    case 0: return launch_cgemm<64, 64, 16>(p, count, m, n, s);
+    case 1: return launch_cgemm<32, 32, 16>(p, count, m, n, s);
+    case 2: return launch_cgemm<128, 64, 16>(p, count, m, n, s);
+    case 3: return launch_cgemm<64, 128, 16>(p, count, m, n, s);
+    case 4: return launch_cgemm<64, 64, 32>(p, count, m, n, s);
+    case 5: return launch_cgemm<32, 64, 16>(p, count, m, n, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+static_assert(kEnvTiles == 6, "launch_env_tile covers every tile shape");
+
 hipError_t launch_env_gemm1_c128(const EnvParent<double2>* items, int count, const double2* site,
-                                 int dl, int dr, hipStream_t s) {
+                                 int dl, int dr, hipStream_t s, int tile) {
   EnvG1P<double> p{items, site, dl, dr};
-  return launch_cgemm<64, 64, 16>(p, count, dl, 2 * dr, s);
+  return launch_env_tile(p, tile, count, dl, 2 * dr, s);
 }
 hipError_t launch_env_gemm2_c128(const EnvChild<double2>* items, int count, const double2* site,
-                                 int dl, int dr, hipStream_t s) {
+                                 int dl, int dr, hipStream_t s, int tile) {
   EnvG2P<double> p{items, site, dl, dr};
-  return launch_cgemm<64, 64, 16>(p, count, dr, dr, s);
+  return launch_env_tile(p, tile, count, dr, dr, s);
 }
 hipError_t launch_env_gemm1_c64(const EnvParent<float2>* items, int count, const float2* site,
-                                int dl, int dr, hipStream_t s) {
+                                int dl, int dr, hipStream_t s, int tile) {
   EnvG1P<float> p{items, site, dl, dr};
-  return launch_cgemm<64, 64, 16>(p, count, dl, 2 * dr, s);
+  return launch_env_tile(p, tile, count, dl, 2 * dr, s);
 }
 hipError_t launch_env_gemm2_c64(const EnvChild<float2>* items, int count, const float2* site,
-                                int dl, int dr, hipStream_t s) {
+                                int dl, int dr, hipStream_t s, int tile) {
   EnvG2P<float> p{items, site, dl, dr};
-  return launch_cgemm<64, 64, 16>(p, count, dr, dr, s);
+  return launch_env_tile(p, tile, count, dr, dr, s);
 }
 
 // split precisions: FP32 environments, 16-bit matrix cores, FP32 accumulation

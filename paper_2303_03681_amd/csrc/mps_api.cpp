@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <unordered_map>
@@ -119,6 +120,7 @@ struct ExpectSetup {
 struct mps_state {
   int n = 0, D = 0, max_sweeps = kDefaultSweeps;
   double cutoff = 0.0;
+  int device = 0;  // current device at create
   hipStream_t stream = nullptr;
   bool own_stream = false;
   size_t budget = 0, held = 0;
@@ -177,6 +179,10 @@ struct mps_state {
   ExpectSetup ex;
   // timing
   bool timing = false;
+  bool autotune = false;               // choose environment GEMM tiles by measurement
+  int forced_tile = -1;                // >= 0: this tile for every environment GEMM
+  std::vector<hipEvent_t> ev_tune;     // tuning pass events
+  size_t ev_tune_used = 0;
   std::vector<hipEvent_t> ev_env, ev_close;
   size_t ev_env_used = 0, ev_close_used = 0;
   hipEvent_t ev_jac[2] = {nullptr, nullptr};
@@ -1097,37 +1103,157 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   return MPS_OK;
 }
 
-mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int prec) {
+// ----------------------------------------------------------------------------
+// tile autotuner for the environment GEMMs (c128, c64)
+//
+// A launch class is (device, precision, GEMM half, D_l, D_r, ceil(log2 items)).
+// The first expectation that meets a class it has no entry for times every
+// tile shape on that launch, twice, and keeps the fastest; the table is
+// process-wide per device.  All shapes give bitwise-identical results, so
+// tuning changes speed only.
+
+struct TuneKey {
+  int dev, prec, half, dl, dr, bucket;
+  bool operator<(const TuneKey& o) const {
+    const int a[6] = {dev, prec, half, dl, dr, bucket}, b[6] = {o.dev, o.prec, o.half, o.dl, o.dr, o.bucket};
+    return std::lexicographical_compare(a, a + 6, b, b + 6);
+  }
+};
+struct TuneEntry {
+  int tile = 0;
+  float ms[kEnvTiles] = {};
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+struct TunePending {
+  TuneKey key;
+  size_t ev0;  // first event of 2 reps x kEnvTiles x (begin, end)
+};
+
+int tune_bucket(int items) {
+  int b = 0;
+  while ((1 << b) < items) ++b;
+  return b;
+}
+
+TuneKey tune_key(const mps_state* h, int prec, int half, const ExpectSetup::EnvLaunch& L) {
+  return TuneKey{h->device, prec, half, L.dl, L.dr, tune_bucket(half == 1 ? L.n_parents : L.n_children)};
+}
+
+// 0: no entry yet (default tile), else the tuned tile.
+int tuned_tile(const TuneKey& k, bool* known) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(k);
+  *known = it != g_tune.end();
+  return *known ? it->second.tile : 0;
+}
+
+hipError_t env_half(mps_state* h, const ExpectSetup::EnvLaunch& L, int prec, int half, const void* site,
+                    int tile) {
   const char* db = (const char*)h->ex.desc;
+  if (prec == MPS_PREC_C128)
+    return half == 1 ? launch_env_gemm1_c128((const EnvParent<double2>*)(db + L.parents_off), L.n_parents,
+                                             (const double2*)site, L.dl, L.dr, h->stream, tile)
+                     : launch_env_gemm2_c128((const EnvChild<double2>*)(db + L.children_off), L.n_children,
+                                             (const double2*)site, L.dl, L.dr, h->stream, tile);
+  if (prec == MPS_PREC_C64)
+    return half == 1 ? launch_env_gemm1_c64((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
+                                            (const float2*)site, L.dl, L.dr, h->stream, tile)
+                     : launch_env_gemm2_c64((const EnvChild<float2>*)(db + L.children_off), L.n_children,
+                                            (const float2*)site, L.dl, L.dr, h->stream, tile);
+  const int f16 = prec == MPS_PREC_SPLIT_F16;
+  return half == 1 ? launch_env_gemm1_split((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
+                                            (const float2*)site, L.dl, L.dr, f16, h->stream)
+                   : launch_env_gemm2_split((const EnvChild<float2>*)(db + L.children_off), L.n_children,
+                                            (const float2*)site, L.dl, L.dr, f16, h->stream);
+}
+
+mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int prec,
+                          std::vector<TunePending>* pending) {
   // resolved per call: the live site buffer flips with every gate
   const void* site_ptr = L.left ? (prec == MPS_PREC_C128 ? (const void*)h->cur(L.site)
                                                          : h->ex.prep[L.site].fwd)
                                 : h->ex.prep[L.site].tr;
-  hipEvent_t b = nullptr, e = nullptr;
-  mps_status st;
-  if (h->timing && (st = timed_begin(h, h->ev_env, h->ev_env_used, b, e)) != MPS_OK) return st;
-  if (prec == MPS_PREC_C128) {
-    HIP_TRY(h, launch_env_gemm1_c128((const EnvParent<double2>*)(db + L.parents_off), L.n_parents,
-                                     (const double2*)site_ptr, L.dl, L.dr, h->stream));
-    HIP_TRY(h, launch_env_gemm2_c128((const EnvChild<double2>*)(db + L.children_off), L.n_children,
-                                     (const double2*)site_ptr, L.dl, L.dr, h->stream));
-  } else if (prec == MPS_PREC_C64) {
-    HIP_TRY(h, launch_env_gemm1_c64((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
-                                    (const float2*)site_ptr, L.dl, L.dr, h->stream));
-    HIP_TRY(h, launch_env_gemm2_c64((const EnvChild<float2>*)(db + L.children_off), L.n_children,
-                                    (const float2*)site_ptr, L.dl, L.dr, h->stream));
-  } else {
-    const int f16 = prec == MPS_PREC_SPLIT_F16;
-    HIP_TRY(h, launch_env_gemm1_split((const EnvParent<float2>*)(db + L.parents_off), L.n_parents,
-                                      (const float2*)site_ptr, L.dl, L.dr, f16, h->stream));
-    HIP_TRY(h, launch_env_gemm2_split((const EnvChild<float2>*)(db + L.children_off), L.n_children,
-                                      (const float2*)site_ptr, L.dl, L.dr, f16, h->stream));
+  const bool tunable = h->autotune && (prec == MPS_PREC_C128 || prec == MPS_PREC_C64);
+  int tile[3] = {0, 0, 0};
+  bool tune[3] = {false, false, false};
+  if (tunable)
+    for (int half = 1; half <= 2; ++half) {
+      bool known = false;
+      const TuneKey k = tune_key(h, prec, half, L);
+      tile[half] = tuned_tile(k, &known);
+      if (!known && pending) {
+        bool queued = false;
+        for (const TunePending& p : *pending)
+          if (!(p.key < k) && !(k < p.key)) queued = true;
+        tune[half] = !queued;
+      }
+    }
+  if (h->forced_tile >= 0 && (prec == MPS_PREC_C128 || prec == MPS_PREC_C64)) {
+    tile[1] = tile[2] = h->forced_tile;
+    tune[1] = tune[2] = false;
   }
+  mps_status st;
+  if (tune[1] || tune[2]) {
+    // a tuning launch: every tile shape twice, bracketed by events; not counted
+    // in the environment timing
+    for (int half = 1; half <= 2; ++half) {
+      if (!tune[half]) {
+        HIP_TRY(h, env_half(h, L, prec, half, site_ptr, tile[half]));
+        continue;
+      }
+      const size_t need = h->ev_tune_used + 4 * kEnvTiles;
+      while (h->ev_tune.size() < need) {
+        hipEvent_t ev;
+        HIP_TRY(h, hipEventCreate(&ev));
+        h->ev_tune.push_back(ev);
+      }
+      pending->push_back(TunePending{tune_key(h, prec, half, L), h->ev_tune_used});
+      for (int rep = 0; rep < 2; ++rep)
+        for (int t = 0; t < kEnvTiles; ++t) {
+          HIP_TRY(h, hipEventRecord(h->ev_tune[h->ev_tune_used++], h->stream));
+          HIP_TRY(h, env_half(h, L, prec, half, site_ptr, t));
+          HIP_TRY(h, hipEventRecord(h->ev_tune[h->ev_tune_used++], h->stream));
+        }
+    }
+    return MPS_OK;
+  }
+  hipEvent_t b = nullptr, e = nullptr;
+  if (h->timing && (st = timed_begin(h, h->ev_env, h->ev_env_used, b, e)) != MPS_OK) return st;
+  HIP_TRY(h, env_half(h, L, prec, 1, site_ptr, tile[1]));
+  HIP_TRY(h, env_half(h, L, prec, 2, site_ptr, tile[2]));
   if (h->timing) {
     HIP_TRY(h, hipEventRecord(e, h->stream));
     h->tm.env_launches += 2;
     h->tm.env_flops += L.flops;
   }
+  return MPS_OK;
+}
+
+// After the stream has drained: the fastest tile of every class tuned in this pass.
+mps_status finish_tuning(mps_state* h, const std::vector<TunePending>& pending) {
+  for (const TunePending& p : pending) {
+    TuneEntry en;
+    float best = 0.f;
+    for (int t = 0; t < kEnvTiles; ++t) {
+      float m = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        const size_t i = p.ev0 + 2 * ((size_t)rep * kEnvTiles + t);
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_tune[i], h->ev_tune[i + 1]));
+        m = rep == 0 ? ms : std::min(m, ms);
+      }
+      en.ms[t] = m;
+      if (t == 0 || m < best) {
+        best = m;
+        en.tile = t;
+      }
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[p.key] = en;
+  }
+  h->ev_tune_used = 0;
   return MPS_OK;
 }
 
@@ -1165,10 +1291,12 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
     for (const auto& r : ex.roots)
       HIP_TRY(h, launch_roots(h->lcur(r.bond), r.lroot, r.rroot, r.d, el, h->stream));
   }
+  std::vector<TunePending> pending;
+  h->ev_tune_used = 0;
   for (const auto& L : ex.left_launches)
-    if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
+    if ((st = run_env_launch(h, L, prec, &pending)) != MPS_OK) return st;
   for (const auto& L : ex.right_launches)
-    if ((st = run_env_launch(h, L, prec)) != MPS_OK) return st;
+    if ((st = run_env_launch(h, L, prec, &pending)) != MPS_OK) return st;
   hipEvent_t b = nullptr, e = nullptr;
   if (h->timing && (st = timed_begin(h, h->ev_close, h->ev_close_used, b, e)) != MPS_OK) return st;
   HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off),
@@ -1191,6 +1319,7 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
                               h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
   if ((st = flush_timing(h)) != MPS_OK) return st;
+  if (!pending.empty() && (st = finish_tuning(h, pending)) != MPS_OK) return st;
   if (!(nn.x > 0.0) || !std::isfinite(nn.x)) return fail(MPS_ERR_NONFINITE, "state norm is zero or not finite");
   if (nrm) h->norm = std::sqrt(nn.x);
   *energy = E;
@@ -1305,6 +1434,7 @@ mps_status mps_create(const mps_config* cfg, mps_handle* out) {
   h->cutoff = cfg->svd_cutoff;
   h->max_sweeps = cfg->max_jacobi_sweeps ? cfg->max_jacobi_sweeps : kDefaultSweeps;
   h->budget = cfg->hbm_budget_bytes;
+  if (hipGetDevice(&h->device) != hipSuccess) return fail(MPS_ERR_DEVICE, "hipGetDevice failed");
   if (cfg->stream) {
     h->stream = (hipStream_t)cfg->stream;
   } else {
@@ -1354,6 +1484,7 @@ mps_status mps_destroy(mps_handle h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (auto& a : h->allocs) (void)hipFree(a.first);
   for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_tune) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_close) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_jac)
     if (e) (void)hipEventDestroy(e);
@@ -1817,6 +1948,55 @@ mps_status mps_set_fused_gates(mps_handle h, int32_t enabled) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;
   h->fused_enabled = enabled != 0;
+  return MPS_OK;
+}
+
+mps_status mps_set_autotune(mps_handle h, int32_t enabled) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  h->autotune = enabled != 0;
+  return MPS_OK;
+}
+
+mps_status mps_set_env_tile(mps_handle h, int32_t tile) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (tile < -1 || tile >= kEnvTiles) return fail(MPS_ERR_ARG, "tile index out of range");
+  h->forced_tile = tile;
+  return MPS_OK;
+}
+
+mps_status mps_autotune_table(char* buf, int64_t cap, int64_t* len) {
+  static const char* prec_name[] = {"c128", "c64", "split_bf16", "split_f16"};
+  std::string out;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& kv : g_tune) {
+      const TuneKey& k = kv.first;
+      const TuneEntry& e = kv.second;
+      const int* sh = kEnvTileShape[e.tile];
+      out += std::to_string(k.dev) + " " + (k.prec >= 0 && k.prec < 4 ? prec_name[k.prec] : "?") + " " +
+             std::to_string(k.half) + " " + std::to_string(k.dl) + " " + std::to_string(k.dr) + " " +
+             std::to_string(k.bucket) + " " + std::to_string(e.tile) + " " + std::to_string(sh[0]) + "x" +
+             std::to_string(sh[1]) + "x" + std::to_string(sh[2]);
+      for (int t = 0; t < kEnvTiles; ++t) {
+        char tmp[32];
+        std::snprintf(tmp, sizeof(tmp), " %.6g", e.ms[t]);
+        out += tmp;
+      }
+      out += "\n";
+    }
+  }
+  if (len) *len = (int64_t)out.size() + 1;
+  if (!buf) return MPS_OK;
+  if (cap < (int64_t)out.size() + 1) return fail(MPS_ERR_ARG, "autotune table buffer too small");
+  std::memcpy(buf, out.c_str(), out.size() + 1);
+  return MPS_OK;
+}
+
+mps_status mps_autotune_reset(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
   return MPS_OK;
 }
 
