@@ -92,6 +92,45 @@ def cpu_baseline(w, n_strings_sample: int = 24, n_gates_sample: int = 2) -> dict
     }
 
 
+def graph_sample(binding, torch, stream, m_big, plan_big) -> dict:
+    """Expectation with the device work replayed as a HIP graph vs eager
+    launches: on the C3 state (few, long launches) and on a 16-qubit D=32
+    fragment (many short launches, where launch overhead shows)."""
+    from workloads import brickwork_gates, fuse_gates, hf_bits, jw_hamiltonian, pack_gates, \
+        random_integrals, workload_rng
+    n_s = 8
+    n = 2 * n_s
+    h, g = random_integrals(n_s, workload_rng(3, 0, 90))
+    ps = jw_hamiltonian(h, g)
+    ang = workload_rng(3, 1, 90).uniform(-np.pi, np.pi, size=(6, n, 2))
+    small = binding.Mps(n, 32, 1e-10, bits=hf_bits(n, n_s), stream=stream.cuda_stream)
+    small.apply_gates(*pack_gates(fuse_gates(brickwork_gates(n, ang), n)))
+    plan_small = binding.PauliSum(ps.codes, ps.coeffs)
+    out = {}
+    for name, m, plan, reps in (("c3_50q_D256", m_big, plan_big, 3),
+                                (f"{n}q_D32_{ps.n_terms}_strings", small, plan_small, 50)):
+        res = {}
+        for prec in ("c64", "c128"):
+            row = {}
+            for mode in ("eager", "graph"):
+                m.set_graphs(mode == "graph")
+                e = m.expect(plan, prec)  # setup / capture (untimed)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(reps):
+                    e2 = m.expect(plan, prec)
+                torch.cuda.synchronize()
+                row[mode + "_ms"] = 1e3 * (time.perf_counter() - t1) / reps
+                row[mode + "_energy"] = e2
+            row["bitwise_equal"] = row["eager_energy"] == row["graph_energy"]
+            res[prec] = row
+            log(f"graph sample {name} {prec}: eager {row['eager_ms']:.2f} ms, graph {row['graph_ms']:.2f} ms")
+        m.set_graphs(False)
+        out[name] = res
+    small.close()
+    return out
+
+
 def serving_sample(n_fragments: int, prec: str) -> dict:
     """A bounded sample of the serving mix: DMET-like fragments (windowed
     UCCSD, own random-integral Hamiltonians) arriving as a Poisson stream at
@@ -267,6 +306,7 @@ def main():
                                        if tp["env_ms"] > 0 else 0.0),
             "energy": e_p,
         }
+    graphs = graph_sample(binding, torch, stream, m, plan)
     e_ref = precisions["c128"]["energy"]
     for pr, d in precisions.items():
         d["abs_dE_vs_c128"] = abs(d["energy"] - e_ref)
@@ -342,6 +382,7 @@ def main():
         "expect_phase_by_precision": precisions,
         "plan": st,
         "autotune": autotune_summary(binding, not args.no_autotune),
+        "expect_graph_vs_eager": graphs,
         "bond_dims_max": int(dims.max()),
         "discarded_weight": disc,
         "roofline": roofline,

@@ -242,6 +242,20 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
  * of mps_get_timing's environment figures.  Off by default. */
 mps_status mps_set_autotune(mps_handle h, int32_t enabled);
 
+/* HIP-graph replay of the expectation (the batching direction's persistent
+ * launch).  With `enabled` != 0, mps_expect_pauli_sum records its device work
+ * from the trie roots to the energy -- every environment update, the closing
+ * traces, the gather and the compensated sum -- into a HIP graph the first
+ * time it meets a (Pauli sum, precision, bond dimensions, root kind)
+ * combination, and afterwards replays that graph with one launch.  Work that
+ * reads the live site and lambda buffers (site preparation, roots, boundary
+ * environments) stays outside the graph and writes the fixed buffers the
+ * graph reads, so a replay after gates sees the new state.  While tile
+ * autotuning still has classes to measure the call runs eagerly.  The graph
+ * holds no memset nodes.  c128 then keeps one more copy of the sites.
+ * Results are bitwise those of the eager path.  Disabling frees the graph. */
+mps_status mps_set_graphs(mps_handle h, int32_t enabled);
+
 /* Use tile shape `tile` (0..5, in the order listed for mps_set_autotune) for
  * every c128/c64 environment GEMM of this handle, overriding the table;
  * -1 (the default) returns to the table or the default tile 0.  For
@@ -275,6 +289,8 @@ typedef struct {
   double jacobi_ms;         /* device time of the multi-launch Jacobi rounds   */
   double jacobi_flops;      /* their algorithmic FLOPs: 32m per rotated pair,   *
                              * 8m per pair visited without rotation (rows of m) */
+  int64_t graph_launches;   /* expectation graphs replayed (mps_set_graphs); the *
+                             * env and close figures above cover eager launches */
 } mps_timing;
 
 mps_status mps_set_timing(mps_handle h, int32_t enabled); /* also resets counters */

@@ -61,6 +61,7 @@ class Timing(C.Structure):
         ("jacobi_sweeps", C.c_int64),
         ("jacobi_ms", C.c_double),
         ("jacobi_flops", C.c_double),
+        ("graph_launches", C.c_int64),
     ]
 
     def as_dict(self):
@@ -98,6 +99,7 @@ _SIGS = {
     "mps_autotune_table": [_P, _I64, _P],
     "mps_autotune_reset": [],
     "mps_set_env_tile": [_P, _I32],
+    "mps_set_graphs": [_P, _I32],
     "mps_apply_gates_multi": [_I32, _P, _P, _P, _P, _P, _P, _P],
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
@@ -289,6 +291,10 @@ class Mps:
     def set_autotune(self, on: bool = True):
         """Choose the environment GEMM tile shapes by measurement (c128, c64)."""
         _check(_lib.mps_set_autotune(self._h, 1 if on else 0))
+
+    def set_graphs(self, on: bool = True):
+        """Replay the expectation's device work as a captured HIP graph."""
+        _check(_lib.mps_set_graphs(self._h, 1 if on else 0))
 
     def set_env_tile(self, tile: int = -1):
         """Force one environment GEMM tile shape (0..5); -1 restores the default."""

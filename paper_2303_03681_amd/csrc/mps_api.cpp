@@ -111,6 +111,11 @@ struct ExpectSetup {
     void* rroot;
   };
   std::vector<RootFill> roots;
+  bool fwd128 = false;             // c128 sites copied to fixed buffers (graph replay)
+  // captured device sequence (environment launches, closes, gather, energy)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_chains = false;       // captured with the boundary-environment norm
   size_t gram_off = 0, tiles_off = 0;
   int gram_items = 0, gram_tiles = 0;
   double gram_flops = 0.0;
@@ -181,6 +186,7 @@ struct mps_state {
   bool timing = false;
   bool autotune = false;               // choose environment GEMM tiles by measurement
   int forced_tile = -1;                // >= 0: this tile for every environment GEMM
+  bool graphs = false;                 // replay the expectation's device work as a HIP graph
   std::vector<hipEvent_t> ev_tune;     // tuning pass events
   size_t ev_tune_used = 0;
   std::vector<hipEvent_t> ev_env, ev_close;
@@ -806,13 +812,24 @@ mps_status flush_timing(mps_state* h) {
   return MPS_OK;
 }
 
+void drop_graph(ExpectSetup& ex) {
+  if (ex.gexec) (void)hipGraphExecDestroy(ex.gexec);
+  if (ex.graph) (void)hipGraphDestroy(ex.graph);
+  ex.gexec = nullptr;
+  ex.graph = nullptr;
+}
+
 mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   ExpectSetup& ex = h->ex;
   const PauliPlan& P = ps->plan;
   const int n = h->n;
-  if (ex.plan_serial == ps->serial && ex.prec == prec && ex.dims == h->dims) return MPS_OK;
+  const bool fwd128 = prec == MPS_PREC_C128 && h->graphs;
+  if (ex.plan_serial == ps->serial && ex.prec == prec && ex.dims == h->dims &&
+      (prec != MPS_PREC_C128 || ex.fwd128 == fwd128))
+    return MPS_OK;
   mps_status st = sync(h);
   if (st != MPS_OK) return st;
+  drop_graph(ex);
   const size_t el = prec == MPS_PREC_C128 ? sizeof(double2) : sizeof(float2);
   const std::vector<int>& D = h->dims;
   // ---- environment pool layout
@@ -849,7 +866,7 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   for (int q = 0; q < n; ++q) {
     const size_t cnt = 2 * (size_t)D[q] * D[q + 1];
     sfwd[q] = site_elems;
-    if (el != sizeof(double2)) site_elems += cnt;
+    if (el != sizeof(double2) || fwd128) site_elems += cnt;
     str[q] = site_elems;
     site_elems += cnt;
   }
@@ -912,7 +929,7 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   };
   ex.prep.clear();
   for (int q = 0; q < n; ++q)
-    ex.prep.push_back({D[q], D[q + 1], el == sizeof(double2) ? nullptr : (void*)(sitep + sfwd[q] * el),
+    ex.prep.push_back({D[q], D[q + 1], el == sizeof(double2) && !fwd128 ? nullptr : (void*)(sitep + sfwd[q] * el),
                        (void*)(sitep + str[q] * el)});
   ex.roots.clear();
   for (int b = 0; b <= n; ++b)
@@ -1100,6 +1117,7 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   ex.plan_serial = ps->serial;
   ex.prec = prec;
   ex.dims = D;
+  ex.fwd128 = fwd128;
   return MPS_OK;
 }
 
@@ -1170,10 +1188,10 @@ hipError_t env_half(mps_state* h, const ExpectSetup::EnvLaunch& L, int prec, int
 }
 
 mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int prec,
-                          std::vector<TunePending>* pending) {
-  // resolved per call: the live site buffer flips with every gate
-  const void* site_ptr = L.left ? (prec == MPS_PREC_C128 ? (const void*)h->cur(L.site)
-                                                         : h->ex.prep[L.site].fwd)
+                          std::vector<TunePending>* pending, bool capturing) {
+  // c128 without a fixed copy reads the live site buffer (it flips with every gate)
+  const void* site_ptr = L.left ? (h->ex.prep[L.site].fwd ? h->ex.prep[L.site].fwd
+                                                          : (const void*)h->cur(L.site))
                                 : h->ex.prep[L.site].tr;
   const bool tunable = h->autotune && (prec == MPS_PREC_C128 || prec == MPS_PREC_C64);
   int tile[3] = {0, 0, 0};
@@ -1220,10 +1238,11 @@ mps_status run_env_launch(mps_state* h, const ExpectSetup::EnvLaunch& L, int pre
     return MPS_OK;
   }
   hipEvent_t b = nullptr, e = nullptr;
-  if (h->timing && (st = timed_begin(h, h->ev_env, h->ev_env_used, b, e)) != MPS_OK) return st;
+  const bool timed = h->timing && !capturing;
+  if (timed && (st = timed_begin(h, h->ev_env, h->ev_env_used, b, e)) != MPS_OK) return st;
   HIP_TRY(h, env_half(h, L, prec, 1, site_ptr, tile[1]));
   HIP_TRY(h, env_half(h, L, prec, 2, site_ptr, tile[2]));
-  if (h->timing) {
+  if (timed) {
     HIP_TRY(h, hipEventRecord(e, h->stream));
     h->tm.env_launches += 2;
     h->tm.env_flops += L.flops;
@@ -1293,23 +1312,70 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   }
   std::vector<TunePending> pending;
   h->ev_tune_used = 0;
-  for (const auto& L : ex.left_launches)
-    if ((st = run_env_launch(h, L, prec, &pending)) != MPS_OK) return st;
-  for (const auto& L : ex.right_launches)
-    if ((st = run_env_launch(h, L, prec, &pending)) != MPS_OK) return st;
-  hipEvent_t b = nullptr, e = nullptr;
-  if (h->timing && (st = timed_begin(h, h->ev_close, h->ev_close_used, b, e)) != MPS_OK) return st;
-  HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off),
-                         (const GramTile*)((char*)ex.desc + ex.tiles_off), ex.gram_tiles, el,
-                         h->stream));
-  if (h->timing) {
-    HIP_TRY(h, hipEventRecord(e, h->stream));
-    h->tm.close_flops += ex.gram_flops;
-    h->tm.env_updates += ex.n_updates;
-  }
   const int64_t T = ps->plan.n_terms;
-  HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, nrm, ex.per_term, T, h->stream));
-  HIP_TRY(h, launch_energy(ex.per_term, ex.coeffs, T, ex.energy, h->stream));
+  // Environment launches, closes, gather and energy: from fixed buffers only
+  // (prepared sites, roots, pool, descriptors), so with graphs enabled they
+  // are captured once per (plan, precision, bond dims, root kind) and replayed.
+  auto device_sequence = [&](bool capturing) -> mps_status {
+    mps_status s2;
+    for (const auto& L : ex.left_launches)
+      if ((s2 = run_env_launch(h, L, prec, capturing ? nullptr : &pending, capturing)) != MPS_OK) return s2;
+    for (const auto& L : ex.right_launches)
+      if ((s2 = run_env_launch(h, L, prec, capturing ? nullptr : &pending, capturing)) != MPS_OK) return s2;
+    hipEvent_t b = nullptr, e = nullptr;
+    const bool timed = h->timing && !capturing;
+    if (timed && (s2 = timed_begin(h, h->ev_close, h->ev_close_used, b, e)) != MPS_OK) return s2;
+    HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off),
+                           (const GramTile*)((char*)ex.desc + ex.tiles_off), ex.gram_tiles, el,
+                           h->stream));
+    if (timed) {
+      HIP_TRY(h, hipEventRecord(e, h->stream));
+      h->tm.close_flops += ex.gram_flops;
+    }
+    if (!capturing && h->timing) h->tm.env_updates += ex.n_updates;
+    HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, nrm, ex.per_term, T, h->stream));
+    HIP_TRY(h, launch_energy(ex.per_term, ex.coeffs, T, ex.energy, h->stream));
+    return MPS_OK;
+  };
+  // a graph only once every tile of this sequence is known (tuning runs eagerly)
+  bool use_graph = h->graphs;
+  if (use_graph && h->autotune && h->forced_tile < 0 && (prec == MPS_PREC_C128 || prec == MPS_PREC_C64))
+    for (int pass = 0; pass < 2 && use_graph; ++pass)
+      for (const auto& L : pass == 0 ? ex.left_launches : ex.right_launches) {
+        bool k1 = false, k2 = false;
+        tuned_tile(tune_key(h, prec, 1, L), &k1);
+        tuned_tile(tune_key(h, prec, 2, L), &k2);
+        if (!k1 || !k2) {
+          use_graph = false;
+          break;
+        }
+      }
+  if (use_graph) {
+    if (ex.gexec && ex.graph_chains != chains) drop_graph(ex);
+    if (!ex.gexec) {
+      HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      const mps_status s_seq = device_sequence(true);
+      hipGraph_t g = nullptr;
+      const hipError_t e_end = hipStreamEndCapture(h->stream, &g);
+      if (s_seq != MPS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s_seq;
+      }
+      if (e_end != hipSuccess) return dev_fail(h, "hipStreamEndCapture", e_end);
+      ex.graph = g;
+      const hipError_t e_inst = hipGraphInstantiate(&ex.gexec, g, nullptr, nullptr, 0);
+      if (e_inst != hipSuccess) {
+        ex.gexec = nullptr;
+        drop_graph(ex);
+        return dev_fail(h, "hipGraphInstantiate", e_inst);
+      }
+      ex.graph_chains = chains;
+    }
+    HIP_TRY(h, hipGraphLaunch(ex.gexec, h->stream));
+    if (h->timing) h->tm.graph_launches += 1;
+  } else if ((st = device_sequence(false)) != MPS_OK) {
+    return st;
+  }
   double E = 0.0;
   double2 nn = make_double2(1.0, 0.0);
   HIP_TRY(h, hipMemcpyAsync(&E, ex.energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -1482,6 +1548,7 @@ mps_status mps_create(const mps_config* cfg, mps_handle* out) {
 mps_status mps_destroy(mps_handle h) {
   if (!h) return MPS_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  drop_graph(h->ex);
   for (auto& a : h->allocs) (void)hipFree(a.first);
   for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_tune) (void)hipEventDestroy(e);
@@ -1958,10 +2025,21 @@ mps_status mps_set_autotune(mps_handle h, int32_t enabled) {
   return MPS_OK;
 }
 
+mps_status mps_set_graphs(mps_handle h, int32_t enabled) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if ((st = sync(h)) != MPS_OK) return st;
+  h->graphs = enabled != 0;
+  if (!h->graphs) drop_graph(h->ex);
+  return MPS_OK;
+}
+
 mps_status mps_set_env_tile(mps_handle h, int32_t tile) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;
   if (tile < -1 || tile >= kEnvTiles) return fail(MPS_ERR_ARG, "tile index out of range");
+  if ((st = sync(h)) != MPS_OK) return st;
+  if (tile != h->forced_tile) drop_graph(h->ex);  // captured with the old tiles
   h->forced_tile = tile;
   return MPS_OK;
 }
