@@ -142,6 +142,16 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* handles,
  * path.  For comparisons and tests. */
 mps_status mps_set_fused_gates(mps_handle h, int32_t enabled);
 
+/* Copy the state of src into dst (site tensors, lambdas, bond dimensions,
+ * canonical flag, norm, discarded weight), device to device on dst's
+ * stream after src's stream has drained; returns when the copy is complete,
+ * so later work on either handle cannot race with it.  Both handles need the same qubit
+ * count and bond capacities (same n_qubits and max_bond); their cutoffs and
+ * sweep limits may differ.  Used for circuit-prefix caching: keep the state
+ * after an unchanged gate prefix and continue copies of it with different
+ * suffixes.  MPS_ERR_ARG for other shapes, dst unchanged. */
+mps_status mps_copy(mps_handle dst, mps_handle src);
+
 /* Restore the exact right-canonical gauge (Eq. rc), exact Schmidt values on
  * every bond and unit norm: a left-to-right orthonormalisation sweep followed
  * by a right-to-left SVD sweep, both by one-sided Jacobi.  Only round-off

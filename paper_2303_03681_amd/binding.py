@@ -100,6 +100,7 @@ _SIGS = {
     "mps_autotune_reset": [],
     "mps_set_env_tile": [_P, _I32],
     "mps_set_graphs": [_P, _I32],
+    "mps_copy": [_P, _P],
     "mps_apply_gates_multi": [_I32, _P, _P, _P, _P, _P, _P, _P],
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
@@ -291,6 +292,10 @@ class Mps:
     def set_autotune(self, on: bool = True):
         """Choose the environment GEMM tile shapes by measurement (c128, c64)."""
         _check(_lib.mps_set_autotune(self._h, 1 if on else 0))
+
+    def copy_from(self, src: "Mps"):
+        """Take src's state (same qubit count and bond capacities)."""
+        _check(_lib.mps_copy(self._h, src._h))
 
     def set_graphs(self, on: bool = True):
         """Replay the expectation's device work as a captured HIP graph."""

@@ -2018,6 +2018,31 @@ mps_status mps_set_fused_gates(mps_handle h, int32_t enabled) {
   return MPS_OK;
 }
 
+mps_status mps_copy(mps_handle dst, mps_handle src) {
+  mps_status st = check_handle(dst);
+  if (st != MPS_OK) return st;
+  if ((st = check_handle(src)) != MPS_OK) return st;
+  if (dst == src) return MPS_OK;
+  if (dst->n != src->n || dst->cap != src->cap)
+    return fail(MPS_ERR_ARG, "mps_copy needs equal qubit counts and bond capacities");
+  if ((st = sync(src)) != MPS_OK) return st;  // src's last gates have landed
+  const int n = src->n;
+  for (int q = 0; q < n; ++q)
+    HIP_TRY(dst, hipMemcpyAsync(dst->cur(q), src->cur(q),
+                                sizeof(double2) * 2 * (size_t)src->dims[q] * src->dims[q + 1],
+                                hipMemcpyDeviceToDevice, dst->stream));
+  for (int b = 0; b <= n; ++b)
+    HIP_TRY(dst, hipMemcpyAsync(dst->lcur(b), src->lcur(b), sizeof(double) * (size_t)src->dims[b],
+                                hipMemcpyDeviceToDevice, dst->stream));
+  // complete before returning: src's next gates may overwrite its buffers in place
+  if ((st = sync(dst)) != MPS_OK) return st;
+  dst->dims = src->dims;
+  dst->canonical = src->canonical;
+  dst->norm = src->norm;
+  dst->discarded = src->discarded;
+  return MPS_OK;
+}
+
 mps_status mps_set_autotune(mps_handle h, int32_t enabled) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;

@@ -32,6 +32,7 @@ from .circuits import (
     gate_swap,
     pauli_exponential_gates,
     uccsd_excitations,
+    uccsd_exponentials,
     uccsd_gates,
     brickwork_gates,
     fuse_gates,
@@ -56,6 +57,7 @@ __all__ = [
     "gate_swap",
     "pauli_exponential_gates",
     "uccsd_excitations",
+    "uccsd_exponentials",
     "uccsd_gates",
     "brickwork_gates",
     "fuse_gates",

@@ -166,21 +166,32 @@ def window_excitations(n_qubits: int, n_electrons: int, window: int = 5):
     return [e for e in singles if ok(*e)], [e for e in doubles if ok(*e)]
 
 
-def uccsd_gates(n_qubits: int, n_electrons: int, theta: np.ndarray, window: int | None = None) -> list[Gate]:
-    """First-order Trotterised UCCSD: prod_ex prod_k exp(i theta_ex c_k P_k).
-    With `window`, only the excitations of window_excitations are used."""
+def uccsd_exponentials(n_qubits: int, n_electrons: int, window: int | None = None):
+    """The Pauli exponentials of first-order Trotterised UCCSD in circuit
+    order: a list of (parameter index j, string codes, c) for the factors
+    exp(i theta_j c P)."""
     if window is None:
         singles, doubles = uccsd_excitations(n_qubits, n_electrons)
     else:
         singles, doubles = window_excitations(n_qubits, n_electrons, window)
     exc = [((a,), (i,)) for (i, a) in singles] + [((a, b), (i, j)) for (i, j, a, b) in doubles]
-    theta = np.asarray(theta, dtype=float)
-    assert theta.size == len(exc), (theta.size, len(exc))
-    gates: list[Gate] = []
-    for t, (left, right) in zip(theta, exc):
+    out = []
+    for j, (left, right) in enumerate(exc):
         codes, c = _generator_strings(n_qubits, left, right)
         for code, ck in zip(codes, c):
-            gates.extend(pauli_exponential_gates(code, float(t * ck)))
+            out.append((j, code, float(ck)))
+    return out
+
+
+def uccsd_gates(n_qubits: int, n_electrons: int, theta: np.ndarray, window: int | None = None) -> list[Gate]:
+    """First-order Trotterised UCCSD: prod_ex prod_k exp(i theta_ex c_k P_k).
+    With `window`, only the excitations of window_excitations are used."""
+    theta = np.asarray(theta, dtype=float)
+    n_par = uccsd_n_params(n_qubits, n_electrons, window)
+    assert theta.size == n_par, (theta.size, n_par)
+    gates: list[Gate] = []
+    for j, code, ck in uccsd_exponentials(n_qubits, n_electrons, window):
+        gates.extend(pauli_exponential_gates(code, float(theta[j] * ck)))
     return gates
 
 
