@@ -213,6 +213,21 @@ mps_status mps_pauli_sum_export(mps_pauli_sum p, int32_t* left_parent, int32_t* 
 mps_status mps_expect_pauli_sum(mps_handle h, mps_pauli_sum p, mps_precision prec, double* energy,
                                 double* per_term);
 
+/* Linear combinations of the expectations of one plan's strings:
+ * out[r] = sum_{i = row_ptr[r]}^{row_ptr[r+1]-1} vals[i] Re<P_{cols[i]}>, for
+ * r < n_rows (CSR on the host; cols index the plan's strings in the order
+ * given to mps_pauli_sum_create; the plan's own coefficients are not used).
+ * The strings are evaluated exactly as by mps_expect_pauli_sum (same roots,
+ * normalisation, precisions); each row is then summed on the device with the
+ * same compensated, order-fixed arithmetic as the energy.  For quantities
+ * such as reduced density matrices: an operator's JW expansion sum v_k P_k
+ * gives Re<O> and Im<O> as two rows with Re v_k and Im v_k.  Row arrays are
+ * validated on the host (row_ptr[0] = 0, non-decreasing, 0 <= cols < number
+ * of strings): MPS_ERR_ARG otherwise. */
+mps_status mps_expect_pauli_rows(mps_handle h, mps_pauli_sum p, mps_precision prec, int64_t n_rows,
+                                 const int64_t* row_ptr, const int64_t* cols, const double* vals,
+                                 double* out);
+
 /* Copy site q's tensor to the host: *dl, *dr receive D_q, D_{q+1}; b (may be
  * NULL) receives 2*D_q*D_{q+1} complex values as (re, im) pairs in
  * [s][alpha][beta] order; lambda_left (may be NULL) receives the D_q

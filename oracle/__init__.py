@@ -7,7 +7,8 @@ binding) never does, and shares no code with it.
 
 Contents
   dense    statevector definition: gates applied to the 2^N vector, Pauli
-           strings applied by bit flip and phase.  With no truncation the MPS
+           strings applied by bit flip and phase; 1- and 2-RDMs from ladder
+           operators applied to the vector.  With no truncation the MPS
            method reaches this result exactly (up to rounding).
   jacobi   one-sided (Hestenes) Jacobi SVD, Algorithm 1 of the paper, written
            for complex matrices.
@@ -32,12 +33,18 @@ from .dense import (
     dense_expect_pauli,
     dense_energy,
     dense_pauli_matrix,
+    dense_annihilate,
+    dense_rdm1,
+    dense_rdm2,
 )
 from .jacobi import one_sided_jacobi_svd
 from .mps import MpsOracle
 
 __all__ = [
     "dense_zero_state",
+    "dense_annihilate",
+    "dense_rdm1",
+    "dense_rdm2",
     "dense_product_state",
     "dense_apply_gate",
     "dense_apply_gates",

@@ -100,3 +100,54 @@ def dense_pauli_matrix(code: np.ndarray) -> np.ndarray:
     for c in code:
         m = np.kron(m, _P1[int(c)])
     return m
+
+
+# --------------------------------------------------------------------------
+# reduced density matrices by ladder operators (Methods, "Density matrix
+# embedding theory": the fragment RDMs the embedding loop needs)
+# --------------------------------------------------------------------------
+
+def dense_annihilate(psi: np.ndarray, j: int) -> np.ndarray:
+    """a_j psi for spin orbital j = qubit j under Jordan-Wigner: the occupied
+    component (bit j = 1) moves to bit j = 0 with sign (-1)^(occupations of
+    qubits 0..j-1)."""
+    n = psi.ndim
+    out = np.zeros_like(psi)
+    src = [slice(None)] * n
+    dst = [slice(None)] * n
+    src[j] = 1
+    dst[j] = 0
+    sub = psi[tuple(src)]  # axes: every qubit but j
+    if j > 0:
+        occ = np.indices((2,) * j).sum(axis=0)  # occupations of qubits < j
+        sign = (1 - 2 * (occ % 2)).reshape((2,) * j + (1,) * (n - 1 - j))
+        sub = sub * sign
+    out[tuple(dst)] = sub
+    return out
+
+
+def dense_rdm1(psi: np.ndarray) -> np.ndarray:
+    """gamma_pq = <a+_p a_q> = (a_p psi)^+ (a_q psi) / <psi|psi>."""
+    n = psi.ndim
+    a = [dense_annihilate(psi, j).reshape(-1) for j in range(n)]
+    nrm = np.vdot(psi.reshape(-1), psi.reshape(-1)).real
+    return np.array([[np.vdot(a[p], a[q]) for q in range(n)] for p in range(n)]) / nrm
+
+
+def dense_rdm2(psi: np.ndarray) -> np.ndarray:
+    """Gamma_pqrs = <a+_p a+_q a_r a_s> = (a_q a_p psi)^+ (a_r a_s psi) / <psi|psi>."""
+    n = psi.ndim
+    two = {}
+    for x in range(n):
+        ax = dense_annihilate(psi, x)
+        for y in range(n):
+            two[(y, x)] = dense_annihilate(ax, y).reshape(-1)  # a_y a_x psi
+    nrm = np.vdot(psi.reshape(-1), psi.reshape(-1)).real
+    g = np.zeros((n, n, n, n), dtype=complex)
+    for p in range(n):
+        for q in range(n):
+            bra = two[(q, p)]
+            for r in range(n):
+                for s in range(n):
+                    g[p, q, r, s] = np.vdot(bra, two[(r, s)])
+    return g / nrm

@@ -101,6 +101,7 @@ _SIGS = {
     "mps_set_env_tile": [_P, _I32],
     "mps_set_graphs": [_P, _I32],
     "mps_copy": [_P, _P],
+    "mps_expect_pauli_rows": [_P, _P, C.c_int, _I64, _P, _P, _P, _P],
     "mps_apply_gates_multi": [_I32, _P, _P, _P, _P, _P, _P, _P],
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
@@ -278,6 +279,17 @@ class Mps:
                                     _ptr(b.view(np.float64)), _ptr(lam)))
 
     # -- expectations -------------------------------------------------------
+    def expect_rows(self, psum: PauliSum, row_ptr, cols, vals, prec: str = "c128") -> np.ndarray:
+        """out[r] = sum over row r of vals[i] * Re<P_cols[i]> (CSR rows)."""
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        n_rows = row_ptr.size - 1
+        out = np.zeros(max(n_rows, 0), np.float64)
+        _check(_lib.mps_expect_pauli_rows(self._h, psum._h, PREC[prec], n_rows, _ptr(row_ptr), _ptr(cols),
+                                          _ptr(vals), _ptr(out)))
+        return out
+
     def expect(self, psum: PauliSum, prec: str = "c128", per_term: bool = False):
         e = C.c_double()
         out = np.zeros(psum.n_terms, np.float64) if per_term else None

@@ -206,6 +206,8 @@ hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int 
                         hipStream_t s);
 hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles,
                        int elem_bytes, hipStream_t s);
+hipError_t launch_rows(const double* per_term, const int64_t* row_ptr, const int64_t* cols, const double* vals,
+                       int64_t n_rows, double* out, hipStream_t s);
 hipError_t launch_gather(const double* g, const int64_t* gidx, const double2* nrm, double* per_term,
                          int64_t n, hipStream_t s);
 hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n, double* out,

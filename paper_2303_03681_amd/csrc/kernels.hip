@@ -1265,6 +1265,33 @@ __global__ __launch_bounds__(1024) void energy_kernel(const double* per_term, co
   if (threadIdx.x == 0) out[0] = hs[0] + ls[0];
 }
 
+// out[r] = sum_{i in row r} vals[i] <P_{cols[i]}>, one thread per row, with
+// the same error-free transformations as the energy (result depends only on
+// the order of the row's entries).
+__global__ void rows_kernel(const double* per_term, const int64_t* row_ptr, const int64_t* cols,
+                           const double* vals, int64_t n_rows, double* out) {
+  const int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (r >= n_rows) return;
+  double s = 0.0, c = 0.0;
+  for (int64_t i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
+    const double p = vals[i] * per_term[cols[i]];
+    const double pe = fma(vals[i], per_term[cols[i]], -p);
+    double t, e;
+    two_sum(s, p, t, e);
+    s = t;
+    c += e + pe;
+  }
+  out[r] = s + c;
+}
+
+hipError_t launch_rows(const double* per_term, const int64_t* row_ptr, const int64_t* cols, const double* vals,
+                       int64_t n_rows, double* out, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s, per_term, row_ptr,
+                     cols, vals, n_rows, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n, double* out,
                          hipStream_t s) {
   hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(1024), 0, s, per_term, coeffs, n, out);

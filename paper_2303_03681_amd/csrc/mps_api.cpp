@@ -116,6 +116,8 @@ struct ExpectSetup {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool graph_chains = false;       // captured with the boundary-environment norm
+  void* rows_buf = nullptr;        // CSR of mps_expect_pauli_rows and its output
+  size_t rows_bytes = 0;
   size_t gram_off = 0, tiles_off = 0;
   int gram_items = 0, gram_tiles = 0;
   double gram_flops = 0.0;
@@ -1276,8 +1278,17 @@ mps_status finish_tuning(mps_state* h, const std::vector<TunePending>& pending) 
   return MPS_OK;
 }
 
+// Linear combinations of the string expectations (CSR, host arrays).
+struct RowsSpec {
+  int64_t n_rows, nnz;
+  const int64_t* row_ptr;
+  const int64_t* cols;
+  const double* vals;
+  double* out;
+};
+
 mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
-                       double* per_term) {
+                       double* per_term, const RowsSpec* rows = nullptr) {
   mps_status st;
   const double t0 = now_ms();
   if ((st = build_expect(h, ps, prec)) != MPS_OK) return st;
@@ -1383,6 +1394,29 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   if (per_term && T)
     HIP_TRY(h, hipMemcpyAsync(per_term, ex.per_term, sizeof(double) * T, hipMemcpyDeviceToHost,
                               h->stream));
+  if (rows && rows->n_rows > 0) {
+    const size_t need = sizeof(int64_t) * (rows->n_rows + 1 + rows->nnz) + sizeof(double) * (rows->nnz + rows->n_rows);
+    if (need > ex.rows_bytes) {
+      if ((st = sync(h)) != MPS_OK) return st;
+      dfree(h, ex.rows_buf);
+      ex.rows_buf = nullptr;
+      ex.rows_bytes = 0;
+      if ((st = dalloc(h, &ex.rows_buf, need)) != MPS_OK) return st;
+      ex.rows_bytes = need;
+    }
+    int64_t* d_ptr = (int64_t*)ex.rows_buf;
+    int64_t* d_cols = d_ptr + rows->n_rows + 1;
+    double* d_vals = (double*)(d_cols + rows->nnz);
+    double* d_out = d_vals + rows->nnz;
+    HIP_TRY(h, hipMemcpyAsync(d_ptr, rows->row_ptr, sizeof(int64_t) * (rows->n_rows + 1), hipMemcpyHostToDevice,
+                              h->stream));
+    if (rows->nnz) {
+      HIP_TRY(h, hipMemcpyAsync(d_cols, rows->cols, sizeof(int64_t) * rows->nnz, hipMemcpyHostToDevice, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(d_vals, rows->vals, sizeof(double) * rows->nnz, hipMemcpyHostToDevice, h->stream));
+    }
+    HIP_TRY(h, launch_rows(ex.per_term, d_ptr, d_cols, d_vals, rows->n_rows, d_out, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(rows->out, d_out, sizeof(double) * rows->n_rows, hipMemcpyDeviceToHost, h->stream));
+  }
   if ((st = sync(h)) != MPS_OK) return st;
   if ((st = flush_timing(h)) != MPS_OK) return st;
   if (!pending.empty() && (st = finish_tuning(h, pending)) != MPS_OK) return st;
@@ -1890,6 +1924,33 @@ mps_status mps_expect_pauli_sum(mps_handle h, mps_pauli_sum p, mps_precision pre
       prec != MPS_PREC_SPLIT_F16)
     return fail(MPS_ERR_ARG, "unknown precision");
   return expect_impl(h, p, (int)prec, energy, per_term);
+}
+
+mps_status mps_expect_pauli_rows(mps_handle h, mps_pauli_sum p, mps_precision prec, int64_t n_rows,
+                                 const int64_t* row_ptr, const int64_t* cols, const double* vals,
+                                 double* out) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!p) return fail(MPS_ERR_ARG, "NULL plan");
+  if (p->plan.n_qubits != h->n) return fail(MPS_ERR_ARG, "plan and MPS qubit counts differ");
+  if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64 && prec != MPS_PREC_SPLIT_BF16 &&
+      prec != MPS_PREC_SPLIT_F16)
+    return fail(MPS_ERR_ARG, "unknown precision");
+  if (n_rows < 0 || (n_rows > 0 && (!row_ptr || !out))) return fail(MPS_ERR_ARG, "bad row arrays");
+  const int64_t T = p->plan.n_terms;
+  int64_t nnz = 0;
+  if (n_rows > 0) {
+    if (row_ptr[0] != 0) return fail(MPS_ERR_ARG, "row_ptr[0] must be 0");
+    for (int64_t r = 0; r < n_rows; ++r)
+      if (row_ptr[r + 1] < row_ptr[r]) return fail(MPS_ERR_ARG, "row_ptr must be non-decreasing");
+    nnz = row_ptr[n_rows];
+    if (nnz > 0 && (!cols || !vals)) return fail(MPS_ERR_ARG, "NULL cols or vals");
+    for (int64_t i = 0; i < nnz; ++i)
+      if (cols[i] < 0 || cols[i] >= T) return fail(MPS_ERR_ARG, "column index out of range");
+  }
+  RowsSpec rs{n_rows, nnz, row_ptr, cols, vals, out};
+  double energy = 0.0;
+  return expect_impl(h, p, (int)prec, &energy, nullptr, &rs);
 }
 
 mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
