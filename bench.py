@@ -37,7 +37,7 @@ PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}  # MI355X dense FP64 / FP32 matrix pe
 # HBM bytes per environment launch on this workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by a 256 MiB copy), environment kernels
 # unchanged since; profiles/env_gemm_traffic_50q_D256.md has the commands and figures.
-ENV_TRAFFIC_BYTES = {"c64": 428.2e6, "c128": 933.1e6, "split_bf16": 429.0e6, "split_f16": 429.0e6}
+ENV_TRAFFIC_BYTES = {"c64": 444.5e6, "c128": None, "split_bf16": 429.0e6, "split_f16": 429.0e6}
 METRIC = "Pauli-string expectations/s at 50q D=256 vs complex128 path; p50/p99 latency"
 
 
@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layers", type=int, default=None, help="override (smaller) layer count")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the graph-replay and gradient samples (e.g. for kernel profiles)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default environment GEMM tile (no tuning in the warmup)")
     ap.add_argument("--serving-fragments", type=int, default=8)
@@ -338,8 +340,8 @@ def main():
                                        if tp["env_ms"] > 0 else 0.0),
             "energy": e_p,
         }
-    graphs = graph_sample(binding, torch, stream, m, plan)
-    grad_sample = gradient_sample(binding, stream)
+    graphs = None if args.no_extras else graph_sample(binding, torch, stream, m, plan)
+    grad_sample = None if args.no_extras else gradient_sample(binding, stream)
     e_ref = precisions["c128"]["energy"]
     for pr, d in precisions.items():
         d["abs_dE_vs_c128"] = abs(d["energy"] - e_ref)
@@ -412,6 +414,7 @@ def main():
                                   if tm["close_ms"] > 0 else 0.0),
                   "gflop_per_step": tm["close_flops"] / K / 1e9},
         "jacobi_sweeps_per_step": tm["jacobi_sweeps"] / K,
+        "jacobi_batch_sweeps_per_step": tm["jacobi_batch_sweeps"] / K,
         "expect_phase_by_precision": precisions,
         "plan": st,
         "autotune": autotune_summary(binding, not args.no_autotune),

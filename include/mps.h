@@ -316,6 +316,8 @@ typedef struct {
                              * 8m per pair visited without rotation (rows of m) */
   int64_t graph_launches;   /* expectation graphs replayed (mps_set_graphs); the *
                              * env and close figures above cover eager launches */
+  int64_t jacobi_batch_sweeps; /* sweeps launched for multi-launch Jacobi batches *
+                                * (a batch runs until its slowest item converges) */
 } mps_timing;
 
 mps_status mps_set_timing(mps_handle h, int32_t enabled); /* also resets counters */

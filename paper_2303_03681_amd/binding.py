@@ -62,6 +62,7 @@ class Timing(C.Structure):
         ("jacobi_ms", C.c_double),
         ("jacobi_flops", C.c_double),
         ("graph_launches", C.c_int64),
+        ("jacobi_batch_sweeps", C.c_int64),
     ]
 
     def as_dict(self):

@@ -442,6 +442,7 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
     int done = 0;
     const int rounds = std::max(jp.reg_rounds, jp.block_rounds);
     for (int sw = 0; sw < h->max_sweeps && done < nmulti; ++sw) {
+      h->tm.jacobi_batch_sweeps += 1;
       for (int r = 0; r < rounds; ++r) {
         if (!jp.reg.empty() && r < jp.reg_rounds)
           HIP_TRY(h, launch_jacobi_reg(d_reg, (int)jp.reg.size(), jp.reg_pairs, r, sw, kEpsScale,
