@@ -61,7 +61,7 @@ class Workload:
 
 def build_config(index: int, fuse: bool = True, with_gates: bool = True,
                  n_spatial: int | None = None, layers: int | None = None,
-                 n_strings: int | None = None) -> Workload:
+                 n_strings: int | None = None, progress=None) -> Workload:
     """Deterministic workload for config ``index``; the keyword overrides
     shrink it (same recipe, smaller sizes) for tests."""
     spec = CONFIGS[index]
@@ -69,7 +69,7 @@ def build_config(index: int, fuse: bool = True, with_gates: bool = True,
     n_q = 2 * n_s
     n_e = min(spec.n_electrons, n_q) if n_spatial is None else min(spec.n_electrons, n_q - 2)
     h, g = random_integrals(n_s, workload_rng(index, PURPOSE_INTEGRALS))
-    full = jw_hamiltonian(h, g)
+    full = jw_hamiltonian(h, g, progress=progress)
     ns = spec.n_strings if n_strings is None else n_strings
     psum = sample_terms(full, ns, workload_rng(index, PURPOSE_SAMPLE)) if ns else full
     bits = hf_bits(n_q, n_e)

@@ -22,6 +22,7 @@ words so that 100-qubit strings fit.
 
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 from math import comb
 
@@ -191,7 +192,30 @@ def _masks_to_codes(keys, n_qubits, words):
     return codes
 
 
-def jw_hamiltonian(h: np.ndarray, g: np.ndarray, drop_rel: float = 1e-15) -> PauliSum:
+def _two_body_chunk(args):
+    """JW expansion of the two-body terms with first orbital p0, like strings combined."""
+    p0, g, words = args
+    n_s = g.shape[0]
+    q, r, s_, sg, tg = np.meshgrid(np.arange(n_s), np.arange(n_s), np.arange(n_s),
+                                   np.arange(2), np.arange(2), indexing="ij")
+    q, r, s_, sg, tg = (a.ravel() for a in (q, r, s_, sg, tg))
+    j1 = 2 * p0 + sg
+    j2 = 2 * r + tg
+    j3 = 2 * s_ + tg
+    j4 = 2 * q + sg
+    keep = (j1 != j2) & (j3 != j4)
+    coef = 0.5 * g[p0, q, r, s_]
+    keep &= coef != 0.0
+    if not np.any(keep):
+        return None, None
+    k2, v2 = _expand_monomials([j1[keep], j2[keep], j3[keep], j4[keep]],
+                               [True, True, False, False],
+                               coef[keep].astype(complex), words)
+    return _reduce(k2, v2)
+
+
+def jw_hamiltonian(h: np.ndarray, g: np.ndarray, drop_rel: float = 1e-15,
+                   workers: int | None = None, progress=None) -> PauliSum:
     """Jordan-Wigner Pauli sum of the spin-orbital Hamiltonian built from (h, g).
 
     Like strings are combined; only round-off residues |c| < drop_rel*max|c|
@@ -211,26 +235,28 @@ def jw_hamiltonian(h: np.ndarray, g: np.ndarray, drop_rel: float = 1e-15) -> Pau
     acc_k.append(k1)
     acc_v.append(v1)
 
-    # two-body, chunked over p: 1/2 (pq|rs) a+_{p s} a+_{r t} a_{s' t} a_{q s}
-    for p0 in range(n_s):
-        q, r, s_, sg, tg = np.meshgrid(np.arange(n_s), np.arange(n_s), np.arange(n_s),
-                                       np.arange(2), np.arange(2), indexing="ij")
-        q, r, s_, sg, tg = (a.ravel() for a in (q, r, s_, sg, tg))
-        j1 = 2 * p0 + sg
-        j2 = 2 * r + tg
-        j3 = 2 * s_ + tg
-        j4 = 2 * q + sg
-        keep = (j1 != j2) & (j3 != j4)
-        coef = 0.5 * g[p0, q, r, s_]
-        keep &= coef != 0.0
-        if not np.any(keep):
-            continue
-        k2, v2 = _expand_monomials([j1[keep], j2[keep], j3[keep], j4[keep]],
-                                   [True, True, False, False],
-                                   coef[keep].astype(complex), words)
-        k2, v2 = _reduce(k2, v2)
-        acc_k.append(k2)
-        acc_v.append(v2)
+    # two-body, chunked over p: 1/2 (pq|rs) a+_{p s} a+_{r t} a_{s' t} a_{q s};
+    # chunks are independent (optionally in worker processes) and concatenated
+    # in p order, so the result does not depend on the number of workers
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if n_s >= 30 else 1
+    args = [(p0, g, words) for p0 in range(n_s)]
+    say = progress or (lambda msg: None)
+    if workers > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        parts = []
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+            for i, part in enumerate(ex.map(_two_body_chunk, args)):
+                parts.append(part)
+                say(f"two-body chunk {i + 1}/{n_s}")
+    else:
+        parts = [_two_body_chunk(a) for a in args]
+    say("combining like strings")
+    for k2, v2 in parts:
+        if k2 is not None:
+            acc_k.append(k2)
+            acc_v.append(v2)
 
     keys, vals = _reduce(np.concatenate(acc_k), np.concatenate(acc_v))
     scale = np.max(np.abs(vals)) if vals.size else 0.0
