@@ -45,15 +45,17 @@ def _cat(parts):
     return q0, q1, u
 
 
-class UccsdGradient:
-    """E(theta) and dE/dtheta of (windowed) UCCSD for one Pauli sum."""
+class ExponentialGradient:
+    """E(theta) and dE/dtheta of a product of Pauli exponentials
+    prod_k exp(i theta_j(k) c_k P_k), given as (j, codes, c) per factor in
+    circuit order, for one Pauli sum."""
 
-    def __init__(self, n_qubits: int, n_electrons: int, plan: "binding.PauliSum", max_bond: int,
-                 cutoff: float = 1e-14, bits=None, window: int | None = None, prec: str = "c128",
-                 batch: int = 8, stream: int | None = None):
+    def __init__(self, n_qubits: int, exps, plan: "binding.PauliSum", max_bond: int,
+                 cutoff: float = 1e-14, bits=None, prec: str = "c128", batch: int = 8,
+                 stream: int | None = None, n_params: int | None = None):
         self.n = int(n_qubits)
-        self.exps = uccsd_exponentials(n_qubits, n_electrons, window)
-        self.n_params = 1 + max((j for j, _, _ in self.exps), default=-1)
+        self.exps = list(exps)
+        self.n_params = n_params if n_params is not None else 1 + max((j for j, _, _ in self.exps), default=-1)
         self.plan = plan
         self.prec = prec
         self.batch = max(1, int(batch))
@@ -138,7 +140,17 @@ class UccsdGradient:
         return e, grad
 
 
-def gradient_descent(grad: UccsdGradient, theta0, steps: int, lr: float):
+class UccsdGradient(ExponentialGradient):
+    """E(theta) and dE/dtheta of (windowed) UCCSD for one Pauli sum."""
+
+    def __init__(self, n_qubits: int, n_electrons: int, plan: "binding.PauliSum", max_bond: int,
+                 cutoff: float = 1e-14, bits=None, window: int | None = None, prec: str = "c128",
+                 batch: int = 8, stream: int | None = None):
+        super().__init__(n_qubits, uccsd_exponentials(n_qubits, n_electrons, window), plan, max_bond,
+                         cutoff, bits, prec, batch, stream)
+
+
+def gradient_descent(grad: ExponentialGradient, theta0, steps: int, lr: float):
     """Plain steepest descent theta <- theta - lr dE/dtheta; returns the
     parameters and the energy before each step and after the last."""
     theta = np.array(theta0, float)

@@ -34,6 +34,8 @@ from .circuits import (
     uccsd_excitations,
     uccsd_exponentials,
     uccsd_gates,
+    gsd_window_excitations,
+    qubit_adapt_pool,
     brickwork_gates,
     fuse_gates,
     pack_gates,
@@ -58,6 +60,8 @@ __all__ = [
     "pauli_exponential_gates",
     "uccsd_excitations",
     "uccsd_exponentials",
+    "gsd_window_excitations",
+    "qubit_adapt_pool",
     "uccsd_gates",
     "brickwork_gates",
     "fuse_gates",

@@ -166,6 +166,53 @@ def window_excitations(n_qubits: int, n_electrons: int, window: int = 5):
     return [e for e in singles if ok(*e)], [e for e in doubles if ok(*e)]
 
 
+def gsd_window_excitations(n_qubits: int, window: int = 5):
+    """Generalised singles and doubles (any orbitals, not only occupied to
+    virtual; spin-conserving) whose spatial orbitals lie within `window`
+    consecutive orbitals, i.e. inside one of the windows starting at every
+    orbital (Methods, ansatz for hydrogen chains).  Singles (p, q), p > q:
+    a+_p a_q; doubles (p, q, r, s), p > q, r > s, (p, q) > (r, s):
+    a+_p a+_q a_r a_s.  Each generator tau - tau^+ appears once."""
+    def ok(*so):
+        sp = [o // 2 for o in so]
+        return max(sp) - min(sp) < window
+    singles = [(p, q) for p in range(n_qubits) for q in range(p)
+               if p % 2 == q % 2 and ok(p, q)]
+    pairs = [(p, q) for p in range(n_qubits) for q in range(p)]
+    doubles = []
+    for (p, q) in pairs:
+        for (r, s) in pairs:
+            if (r, s) >= (p, q):
+                continue
+            if sorted((p % 2, q % 2)) != sorted((r % 2, s % 2)):
+                continue
+            if ok(p, q, r, s):
+                doubles.append((p, q, r, s))
+    return singles, doubles
+
+
+def qubit_adapt_pool(n_qubits: int, window: int = 5) -> np.ndarray:
+    """Operator pool of the windowed qubit-ADAPT ansatz: the JW strings of
+    every windowed GSD generator with all Z letters removed, strings with an
+    even number of Y dropped (the Hamiltonian is real), duplicates merged.
+    Returns codes (P, n_qubits) uint8 in lexicographic order."""
+    singles, doubles = gsd_window_excitations(n_qubits, window)
+    rows = []
+    for (p, q) in singles:
+        codes, _ = _generator_strings(n_qubits, (p,), (q,))
+        rows.append(codes)
+    for (p, q, r, s) in doubles:
+        codes, _ = _generator_strings(n_qubits, (p, q), (r, s))
+        rows.append(codes)
+    if not rows:
+        return np.zeros((0, n_qubits), np.uint8)
+    codes = np.concatenate(rows).copy()
+    codes[codes == CODE_Z] = CODE_I
+    odd_y = (np.sum(codes == CODE_Y, axis=1) % 2) == 1
+    codes = np.unique(codes[odd_y], axis=0)
+    return np.ascontiguousarray(codes[np.lexsort(codes.T[::-1])], dtype=np.uint8)
+
+
 def uccsd_exponentials(n_qubits: int, n_electrons: int, window: int | None = None):
     """The Pauli exponentials of first-order Trotterised UCCSD in circuit
     order: a list of (parameter index j, string codes, c) for the factors
