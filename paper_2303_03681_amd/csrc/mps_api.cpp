@@ -194,6 +194,10 @@ struct mps_state {
   std::vector<hipEvent_t> ev_env, ev_close;
   size_t ev_env_used = 0, ev_close_used = 0;
   hipEvent_t ev_jac[2] = {nullptr, nullptr};
+  // second stream (default priority): one-workgroup SVDs of small gates run
+  // beside the multi-launch rounds of the large gates of the same batch
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   mps_timing tm{};
 
   double2* cur(int q) { return site[site_cur[q]][q]; }
@@ -285,6 +289,14 @@ mps_status upload(mps_state* h, void* dst, const void* src, size_t bytes) {
 
 mps_status sync(mps_state* h) {
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return MPS_OK;
+}
+
+mps_status ensure_side(mps_state* h) {
+  if (h->side) return MPS_OK;
+  HIP_TRY(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  HIP_TRY(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   return MPS_OK;
 }
 
@@ -420,11 +432,32 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   packed.insert(packed.end(), jp.reg.begin(), jp.reg.end());
   packed.insert(packed.end(), jp.block.begin(), jp.block.end());
   if ((st = upload(h, base, packed.data(), bytes)) != MPS_OK) return st;
+  const int nmulti_items = (int)(jp.reg.size() + jp.block.size());
+  const bool overlap = nmulti_items > 0 && (!jp.small.empty() || !jp.single.empty());
+  hipStream_t one_stream = h->stream;
+  if (overlap) {
+    if ((st = ensure_side(h)) != MPS_OK) return st;
+    HIP_TRY(h, hipEventRecord(h->ev_fork, h->stream));
+    HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    one_stream = h->side;
+  }
   if (!jp.small.empty())
-    HIP_TRY(h, launch_jacobi_small(d_small, (int)jp.small.size(), h->max_sweeps, kEpsScale, h->stream));
+    HIP_TRY(h, launch_jacobi_small(d_small, (int)jp.small.size(), h->max_sweeps, kEpsScale, one_stream));
   if (!jp.single.empty())
     HIP_TRY(h, launch_jacobi_single(d_single, (int)jp.single.size(), h->max_sweeps, kEpsScale,
-                                    jp.single_lds, h->stream));
+                                    jp.single_lds, one_stream));
+  // every later use of the handle's stream (also on an early return) waits for them
+  struct Join {
+    mps_state* h;
+    bool on;
+    ~Join() {
+      if (on) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
+    }
+  } join{h, false};
+  if (overlap) {
+    HIP_TRY(h, hipEventRecord(h->ev_join, h->side));
+    join.on = true;
+  }
   // per item (caller order): first rotation-free sweep, from the counters
   std::vector<int> first_zero(count, -1);
   std::vector<char> is_multi(count, 0);
@@ -487,6 +520,10 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
         }
       }
     }
+  }
+  if (join.on) {
+    HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+    join.on = false;
   }
   // one-launch items report their sweeps themselves
   std::vector<JacItem> one(jp.small);
@@ -1583,6 +1620,7 @@ mps_status mps_create(const mps_config* cfg, mps_handle* out) {
 mps_status mps_destroy(mps_handle h) {
   if (!h) return MPS_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->side) (void)hipStreamSynchronize(h->side);
   drop_graph(h->ex);
   for (auto& a : h->allocs) (void)hipFree(a.first);
   for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
@@ -1590,6 +1628,9 @@ mps_status mps_destroy(mps_handle h) {
   for (hipEvent_t e : h->ev_close) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_jac)
     if (e) (void)hipEventDestroy(e);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return MPS_OK;
