@@ -164,6 +164,8 @@ hipError_t launch_mix(const MixItem* items_dev, int items, int max_dldr, hipStre
 hipError_t configure_jacobi_lds(size_t bytes);
 hipError_t launch_jacobi_block(const JacItem* items_dev, int items, int max_pairs, int round,
                                int sweep, double eps_scale, size_t lds_bytes, hipStream_t s);
+hipError_t launch_jacobi_wide(const JacItem* items_dev, int items, int max_pairs, int round, int sweep,
+                              double eps_scale, hipStream_t s);
 hipError_t launch_jacobi_reg(const JacItem* items_dev, int items, int max_pairs, int round,
                              int sweep, double eps_scale, int max_m, hipStream_t s);
 hipError_t launch_jacobi_single(const JacItem* items_dev, int items, int max_sweeps,

@@ -588,6 +588,114 @@ hipError_t launch_reg_e(const JacItem* items_dev, int items, int max_pairs, int 
   return hipGetLastError();
 }
 
+// Rows of 513..1024 elements (E = 16, 64 registers per row and lane): a wave
+// keeps one resident row of block bp in registers and takes its partners
+// from LDS, where the eight rows of block bq sit (128 KB).  Cross rounds are
+// eight steps; at step st wave w pairs its resident row with LDS row
+// (w + st) % 8, a permutation, so no row is touched twice in a step.  Outer
+// round 0 first sweeps the 28 pairs inside each block (block bp, then bq, in
+// LDS, circle method, four waves with both rows in registers), then the 64
+// cross pairs, so that every pair is visited once per outer sweep as with
+// the shorter rows.
+constexpr int WW = 8;  // waves per workgroup = rows per block
+
+template <int E>
+__device__ __forceinline__ int wide_intra_block(double2* lds, int b, int n, double eps, double floor,
+                                                int wv, int lane) {
+  int rot = 0;
+  for (int t = 0; t < WW - 1; ++t) {
+    if (wv < WW / 2) {
+      auto pos = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + t) % (WW - 1); };
+      const int a = pos(wv), bb = pos(WW - 1 - wv);
+      const int ga = b * WW + a, gb = b * WW + bb;
+      RegVec<E> x, y;
+      rv_from_lds<E>(x, lds + (size_t)a * 64 * E, lane);
+      rv_from_lds<E>(y, lds + (size_t)bb * 64 * E, lane);
+      if (jacobi_pair_ordered<E>(x, ga < n ? ga : -1, y, gb < n ? gb : -1, eps, floor)) {
+        rv_to_lds<E>(x, lds + (size_t)a * 64 * E, lane);
+        rv_to_lds<E>(y, lds + (size_t)bb * 64 * E, lane);
+        ++rot;
+      }
+    }
+    __syncthreads();
+  }
+  return rot;
+}
+
+template <int E>
+__global__ __launch_bounds__(WW * 64, 1) void jacobi_reg_wide_kernel(const JacItem* items, int max_pairs,
+                                                                     int round, int sweep,
+                                                                     double eps_scale) {
+  extern __shared__ double2 lds[];  // WW rows of 64 E elements
+  __shared__ int s_rot;
+  RegCtx c;
+  if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
+  const int m = c.it.m, n = c.it.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_rot = 0;
+  int rot = 0;
+  auto block_to_lds = [&](int b) {
+    const int g = b * WW + wv;
+    RegVec<E> t;
+    rv_load<E>(t, c.it.w + (size_t)min(g, n - 1) * m, g < n, m, lane);
+    rv_to_lds<E>(t, lds + (size_t)wv * 64 * E, lane);
+  };
+  const int gx = c.bp * WW + wv;
+  if (round == 0) {
+    // block bp's own pairs in LDS; its rows go back to memory (each lane
+    // rewrites and later rereads only its own elements) so that no resident
+    // row is held while the other block's pairs take two rows per wave
+    block_to_lds(c.bp);
+    __syncthreads();
+    const int r0 = wide_intra_block<E>(lds, c.bp, n, c.eps, c.floor, wv, lane);
+    rot += r0;
+    if (gx < n) {
+      RegVec<E> t;
+      rv_from_lds<E>(t, lds + (size_t)wv * 64 * E, lane);
+      rv_store<E>(t, c.it.w + (size_t)gx * m, m, lane);
+    }
+    __syncthreads();  // every row is read before block bq overwrites LDS
+  }
+  block_to_lds(c.bq);
+  __syncthreads();
+  if (round == 0) rot += wide_intra_block<E>(lds, c.bq, n, c.eps, c.floor, wv, lane);
+  RegVec<E> x;  // resident row wv of block bp
+  rv_load<E>(x, c.it.w + (size_t)min(gx, n - 1) * m, gx < n, m, lane);
+  for (int st = 0; st < WW; ++st) {
+    const int j = (wv + st) % WW;
+    const int gy = c.bq * WW + j;
+    RegVec<E> y;
+    rv_from_lds<E>(y, lds + (size_t)j * 64 * E, lane);
+    if (jacobi_pair_ordered<E>(x, gx < n ? gx : -1, y, gy < n ? gy : -1, c.eps, c.floor)) {
+      rv_to_lds<E>(y, lds + (size_t)j * 64 * E, lane);
+      ++rot;
+    }
+    __syncthreads();
+  }
+  if (lane == 0 && rot) atomicAdd(&s_rot, rot);
+  __syncthreads();
+  if (s_rot > 0) {
+    if (gx < n) rv_store<E>(x, c.it.w + (size_t)gx * m, m, lane);
+    const int gq = c.bq * WW + wv;
+    if (gq < n) {
+      RegVec<E> t;
+      rv_from_lds<E>(t, lds + (size_t)wv * 64 * E, lane);
+      rv_store<E>(t, c.it.w + (size_t)gq * m, m, lane);
+    }
+    if (threadIdx.x == 0) atomicAdd(&c.it.rot[sweep * c.it.rot_stride], s_rot);
+  }
+}
+
+constexpr size_t kWideLds = (size_t)WW * 64 * 16 * sizeof(double2);
+
+hipError_t launch_jacobi_wide(const JacItem* items_dev, int items, int max_pairs, int round, int sweep,
+                              double eps_scale, hipStream_t s) {
+  if (items <= 0 || max_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_reg_wide_kernel<16>, dim3(items * max_pairs), dim3(WW * 64), kWideLds, s,
+                     items_dev, max_pairs, round, sweep, eps_scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobi_reg(const JacItem* items_dev, int items, int max_pairs, int round,
                              int sweep, double eps_scale, int max_m, hipStream_t s) {
   if (items <= 0 || max_pairs <= 0) return hipSuccess;
@@ -637,6 +745,11 @@ hipError_t configure_jacobi_lds(size_t bytes) {
                        (const void*)jacobi_reg_cross_kernel<4>, (const void*)jacobi_reg_cross_kernel<8>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  if (bytes >= kWideLds) {
+    hipError_t e = hipFuncSetAttribute((const void*)jacobi_reg_wide_kernel<16>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWideLds);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

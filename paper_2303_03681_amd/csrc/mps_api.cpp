@@ -352,14 +352,17 @@ mps_status ensure_ws(mps_state* h, int items) {
 struct JacobiPlanHost {
   std::vector<JacItem> small;               // register single-launch (n, m <= 128)
   std::vector<JacItem> single, reg, block;  // LDS single-launch, register blocks, LDS blocks
+  std::vector<JacItem> wide;                // register blocks of 513..1024-long rows
   size_t single_lds = 0, block_lds = 0;
   int reg_pairs = 0, reg_rounds = 0, reg_max_m = 0;
   int block_pairs = 0, block_rounds = 0;
+  int wide_pairs = 0, wide_rounds = 0;
 };
 
 constexpr int kRegBlock = 8;     // vectors per block of the register kernels (one per wave)
 constexpr int kRegMaxLen = 512;  // longest vector the register kernels hold
 constexpr int kSmallMax = 128;   // rows and row length of the one-workgroup register kernel
+constexpr size_t kWideLdsBytes = (size_t)kRegBlock * 2 * kRegMaxLen * sizeof(double2);  // one block in LDS
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
@@ -390,6 +393,14 @@ void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
       jp.reg_pairs = std::max(jp.reg_pairs, nb / 2);
       jp.reg_rounds = std::max(jp.reg_rounds, nb - 1);
       jp.reg_max_m = std::max(jp.reg_max_m, it.m);
+    } else if (it.m <= 2 * kRegMaxLen && budget >= kWideLdsBytes) {
+      int nb = (it.n + kRegBlock - 1) / kRegBlock;
+      if (nb & 1) ++nb;
+      it.wblk = kRegBlock;
+      it.nb = nb;
+      jp.wide.push_back(it);
+      jp.wide_pairs = std::max(jp.wide_pairs, nb / 2);
+      jp.wide_rounds = std::max(jp.wide_rounds, nb - 1);
     } else {
       const int max_vec = (int)std::max<size_t>(2, budget / per_vec);
       int w = std::min(128, max_vec / 2);
@@ -419,7 +430,8 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   JacobiPlanHost jp;
   plan_jacobi(all, jp);
   const size_t bytes =
-      (jp.small.size() + jp.single.size() + jp.reg.size() + jp.block.size()) * sizeof(JacItem);
+      (jp.small.size() + jp.single.size() + jp.reg.size() + jp.block.size() + jp.wide.size()) *
+      sizeof(JacItem);
   mps_status st = ensure_desc(h, desc_off + bytes);
   if (st != MPS_OK) return st;
   char* base = (char*)h->d_desc + desc_off;
@@ -427,12 +439,14 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   JacItem* d_single = d_small + jp.small.size();
   JacItem* d_reg = d_single + jp.single.size();
   JacItem* d_block = d_reg + jp.reg.size();
+  JacItem* d_wide = d_block + jp.block.size();
   std::vector<JacItem> packed(jp.small);
   packed.insert(packed.end(), jp.single.begin(), jp.single.end());
   packed.insert(packed.end(), jp.reg.begin(), jp.reg.end());
   packed.insert(packed.end(), jp.block.begin(), jp.block.end());
+  packed.insert(packed.end(), jp.wide.begin(), jp.wide.end());
   if ((st = upload(h, base, packed.data(), bytes)) != MPS_OK) return st;
-  const int nmulti_items = (int)(jp.reg.size() + jp.block.size());
+  const int nmulti_items = (int)(jp.reg.size() + jp.block.size() + jp.wide.size());
   const bool overlap = nmulti_items > 0 && (!jp.small.empty() || !jp.single.empty());
   hipStream_t one_stream = h->stream;
   if (overlap) {
@@ -463,7 +477,8 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   std::vector<char> is_multi(count, 0);
   for (const JacItem& b : jp.reg) is_multi[b.rot - all[0].rot] = 1;
   for (const JacItem& b : jp.block) is_multi[b.rot - all[0].rot] = 1;
-  const int nmulti = (int)(jp.reg.size() + jp.block.size());
+  for (const JacItem& b : jp.wide) is_multi[b.rot - all[0].rot] = 1;
+  const int nmulti = nmulti_items;
   const bool timed = h->timing && nmulti > 0;
   if (timed) {
     for (hipEvent_t& ev : h->ev_jac)
@@ -473,7 +488,7 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   if (nmulti > 0) {
     std::vector<int> rot(count);
     int done = 0;
-    const int rounds = std::max(jp.reg_rounds, jp.block_rounds);
+    const int rounds = std::max(std::max(jp.reg_rounds, jp.block_rounds), jp.wide_rounds);
     for (int sw = 0; sw < h->max_sweeps && done < nmulti; ++sw) {
       h->tm.jacobi_batch_sweeps += 1;
       for (int r = 0; r < rounds; ++r) {
@@ -483,6 +498,9 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
         if (!jp.block.empty() && r < jp.block_rounds)
           HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
                                          kEpsScale, jp.block_lds, h->stream));
+        if (!jp.wide.empty() && r < jp.wide_rounds)
+          HIP_TRY(h, launch_jacobi_wide(d_wide, (int)jp.wide.size(), jp.wide_pairs, r, sw, kEpsScale,
+                                        h->stream));
       }
       if (sw >= 3 || sw == h->max_sweeps - 1) {
         HIP_TRY(h, hipMemcpyAsync(rot.data(), all[0].rot + (size_t)sw * count, sizeof(int) * count,

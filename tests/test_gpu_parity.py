@@ -55,7 +55,8 @@ def test_mfma_layout(gpu_lib):
 
 
 @pytest.mark.parametrize("n,m", [(4, 6), (16, 16), (33, 20), (64, 64), (20, 300), (96, 512),
-                                 (200, 64), (512, 512), (40, 700), (18, 18)])
+                                 (200, 64), (512, 512), (40, 700), (18, 18), (1024, 1024),
+                                 (300, 1000), (1000, 520), (1023, 1022)])
 def test_jacobi_svd_matches_lapack(gpu_lib, n, m):
     from paper_2303_03681_amd import binding
     _say(f"jacobi n={n} m={m}")
