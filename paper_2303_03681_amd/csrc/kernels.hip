@@ -597,17 +597,15 @@ hipError_t launch_reg_e(const JacItem* items_dev, int items, int max_pairs, int 
 // LDS, circle method, four waves with both rows in registers), then the 64
 // cross pairs, so that every pair is visited once per outer sweep as with
 // the shorter rows.
-constexpr int WW = 8;  // waves per workgroup = rows per block
-
-template <int E>
-__device__ __forceinline__ int wide_intra_block(double2* lds, int b, int n, double eps, double floor,
-                                                int wv, int lane) {
+template <int E, int NW>
+__device__ __forceinline__ int lds_intra_block(double2* lds, int b, int n, double eps, double floor, int wv,
+                                               int lane) {
   int rot = 0;
-  for (int t = 0; t < WW - 1; ++t) {
-    if (wv < WW / 2) {
-      auto pos = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + t) % (WW - 1); };
-      const int a = pos(wv), bb = pos(WW - 1 - wv);
-      const int ga = b * WW + a, gb = b * WW + bb;
+  for (int t = 0; t < NW - 1; ++t) {
+    if (wv < NW / 2) {
+      auto pos = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + t) % (NW - 1); };
+      const int a = pos(wv), bb = pos(NW - 1 - wv);
+      const int ga = b * NW + a, gb = b * NW + bb;
       RegVec<E> x, y;
       rv_from_lds<E>(x, lds + (size_t)a * 64 * E, lane);
       rv_from_lds<E>(y, lds + (size_t)bb * 64 * E, lane);
@@ -622,48 +620,60 @@ __device__ __forceinline__ int wide_intra_block(double2* lds, int b, int n, doub
   return rot;
 }
 
-template <int E>
-__global__ __launch_bounds__(WW * 64, 1) void jacobi_reg_wide_kernel(const JacItem* items, int max_pairs,
-                                                                     int round, int sweep,
-                                                                     double eps_scale) {
-  extern __shared__ double2 lds[];  // WW rows of 64 E elements
+// Blocks of NW rows on NW waves: each wave keeps one resident row of block bp
+// in registers and takes its partners from LDS, where the NW rows of block bq
+// sit (NW * 64 E complex values).  Cross rounds are NW steps; at step st wave
+// w pairs its resident row with LDS row (w + st) % NW, a permutation, so no
+// row is touched twice in a step.  Outer round 0 first sweeps the pairs
+// inside each block (block bp, then bq, in LDS, circle method, NW / 2 waves
+// with both rows in registers), then the cross pairs, so that every pair is
+// visited once per outer sweep.  Used with E = 16 (513..1024-long rows) and
+// NW = 8, the block size of the other register kernels.
+template <int E, int NW>
+__global__ __launch_bounds__(NW * 64, 1) void jacobi_reg_lds_kernel(const JacItem* items, int max_pairs,
+                                                                    int round, int sweep, double eps_scale) {
+  extern __shared__ double2 lds[];  // NW rows of 64 E elements
   __shared__ int s_rot;
   RegCtx c;
   if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
   const int m = c.it.m, n = c.it.n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the block pair in units of NW rows (the prologue's indices are in units of the item's blocks)
+  const int bp = c.bp, bq = c.bq;
   if (threadIdx.x == 0) s_rot = 0;
   int rot = 0;
   auto block_to_lds = [&](int b) {
-    const int g = b * WW + wv;
-    RegVec<E> t;
-    rv_load<E>(t, c.it.w + (size_t)min(g, n - 1) * m, g < n, m, lane);
-    rv_to_lds<E>(t, lds + (size_t)wv * 64 * E, lane);
+    const int g = b * NW + wv;
+    const double2* src = c.it.w + (size_t)min(g, n - 1) * m;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = lane + 64 * k;
+      lds[(size_t)wv * 64 * E + 64 * k + lane] = (g < n && e < m) ? src[e] : make_double2(0.0, 0.0);
+    }
   };
-  const int gx = c.bp * WW + wv;
+  const int gx = bp * NW + wv;
   if (round == 0) {
     // block bp's own pairs in LDS; its rows go back to memory (each lane
     // rewrites and later rereads only its own elements) so that no resident
     // row is held while the other block's pairs take two rows per wave
-    block_to_lds(c.bp);
+    block_to_lds(bp);
     __syncthreads();
-    const int r0 = wide_intra_block<E>(lds, c.bp, n, c.eps, c.floor, wv, lane);
-    rot += r0;
-    if (gx < n) {
-      RegVec<E> t;
-      rv_from_lds<E>(t, lds + (size_t)wv * 64 * E, lane);
-      rv_store<E>(t, c.it.w + (size_t)gx * m, m, lane);
-    }
+    rot += lds_intra_block<E, NW>(lds, bp, n, c.eps, c.floor, wv, lane);
+    if (gx < n)
+      for (int k = 0; k < E; ++k) {
+        const int e = lane + 64 * k;
+        if (e < m) c.it.w[(size_t)gx * m + e] = lds[(size_t)wv * 64 * E + 64 * k + lane];
+      }
     __syncthreads();  // every row is read before block bq overwrites LDS
   }
-  block_to_lds(c.bq);
+  block_to_lds(bq);
   __syncthreads();
-  if (round == 0) rot += wide_intra_block<E>(lds, c.bq, n, c.eps, c.floor, wv, lane);
+  if (round == 0) rot += lds_intra_block<E, NW>(lds, bq, n, c.eps, c.floor, wv, lane);
   RegVec<E> x;  // resident row wv of block bp
   rv_load<E>(x, c.it.w + (size_t)min(gx, n - 1) * m, gx < n, m, lane);
-  for (int st = 0; st < WW; ++st) {
-    const int j = (wv + st) % WW;
-    const int gy = c.bq * WW + j;
+  for (int st = 0; st < NW; ++st) {
+    const int j = (wv + st) % NW;
+    const int gy = bq * NW + j;
     RegVec<E> y;
     rv_from_lds<E>(y, lds + (size_t)j * 64 * E, lane);
     if (jacobi_pair_ordered<E>(x, gx < n ? gx : -1, y, gy < n ? gy : -1, c.eps, c.floor)) {
@@ -676,22 +686,26 @@ __global__ __launch_bounds__(WW * 64, 1) void jacobi_reg_wide_kernel(const JacIt
   __syncthreads();
   if (s_rot > 0) {
     if (gx < n) rv_store<E>(x, c.it.w + (size_t)gx * m, m, lane);
-    const int gq = c.bq * WW + wv;
-    if (gq < n) {
-      RegVec<E> t;
-      rv_from_lds<E>(t, lds + (size_t)wv * 64 * E, lane);
-      rv_store<E>(t, c.it.w + (size_t)gq * m, m, lane);
-    }
+    const int gq = bq * NW + wv;
+    if (gq < n)
+      for (int k = 0; k < E; ++k) {
+        const int e = lane + 64 * k;
+        if (e < m) c.it.w[(size_t)gq * m + e] = lds[(size_t)wv * 64 * E + 64 * k + lane];
+      }
     if (threadIdx.x == 0) atomicAdd(&c.it.rot[sweep * c.it.rot_stride], s_rot);
   }
 }
 
-constexpr size_t kWideLds = (size_t)WW * 64 * 16 * sizeof(double2);
+constexpr size_t kWideLds = (size_t)8 * 64 * 16 * sizeof(double2);  // 128 KB
 
+// Rows of 513..1024 elements: E = 16, 8-row blocks.  (The same design with
+// E = 8 and 16-row blocks, half the rounds of the 8-row register blocks, was
+// slower than jacobi_reg_cross_kernel on 512-long rows: 159 against 101 ms
+// per saturated 50-qubit D = 256 layer.)
 hipError_t launch_jacobi_wide(const JacItem* items_dev, int items, int max_pairs, int round, int sweep,
                               double eps_scale, hipStream_t s) {
   if (items <= 0 || max_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_reg_wide_kernel<16>, dim3(items * max_pairs), dim3(WW * 64), kWideLds, s,
+  hipLaunchKernelGGL((jacobi_reg_lds_kernel<16, 8>), dim3(items * max_pairs), dim3(8 * 64), kWideLds, s,
                      items_dev, max_pairs, round, sweep, eps_scale);
   return hipGetLastError();
 }
@@ -748,9 +762,11 @@ hipError_t configure_jacobi_lds(size_t bytes) {
     if (e != hipSuccess) return e;
   }
   if (bytes >= kWideLds) {
-    hipError_t e = hipFuncSetAttribute((const void*)jacobi_reg_wide_kernel<16>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWideLds);
-    if (e != hipSuccess) return e;
+    const void* lf[] = {(const void*)jacobi_reg_lds_kernel<16, 8>};
+    for (const void* f : lf) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWideLds);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -352,7 +352,7 @@ mps_status ensure_ws(mps_state* h, int items) {
 struct JacobiPlanHost {
   std::vector<JacItem> small;               // register single-launch (n, m <= 128)
   std::vector<JacItem> single, reg, block;  // LDS single-launch, register blocks, LDS blocks
-  std::vector<JacItem> wide;                // register blocks of 513..1024-long rows
+  std::vector<JacItem> wide;                // 513..1024-long rows: partner block in LDS
   size_t single_lds = 0, block_lds = 0;
   int reg_pairs = 0, reg_rounds = 0, reg_max_m = 0;
   int block_pairs = 0, block_rounds = 0;
@@ -384,6 +384,14 @@ void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
       it.nb = 1;
       jp.single.push_back(it);
       jp.single_lds = std::max(jp.single_lds, (size_t)it.n * per_vec);
+    } else if (it.m > kRegMaxLen && it.m <= 2 * kRegMaxLen && budget >= kWideLdsBytes) {
+      int nb = (it.n + kRegBlock - 1) / kRegBlock;
+      if (nb & 1) ++nb;
+      it.wblk = kRegBlock;
+      it.nb = nb;
+      jp.wide.push_back(it);
+      jp.wide_pairs = std::max(jp.wide_pairs, nb / 2);
+      jp.wide_rounds = std::max(jp.wide_rounds, nb - 1);
     } else if (it.m <= kRegMaxLen) {
       int nb = (it.n + kRegBlock - 1) / kRegBlock;
       if (nb & 1) ++nb;
@@ -393,14 +401,6 @@ void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
       jp.reg_pairs = std::max(jp.reg_pairs, nb / 2);
       jp.reg_rounds = std::max(jp.reg_rounds, nb - 1);
       jp.reg_max_m = std::max(jp.reg_max_m, it.m);
-    } else if (it.m <= 2 * kRegMaxLen && budget >= kWideLdsBytes) {
-      int nb = (it.n + kRegBlock - 1) / kRegBlock;
-      if (nb & 1) ++nb;
-      it.wblk = kRegBlock;
-      it.nb = nb;
-      jp.wide.push_back(it);
-      jp.wide_pairs = std::max(jp.wide_pairs, nb / 2);
-      jp.wide_rounds = std::max(jp.wide_rounds, nb - 1);
     } else {
       const int max_vec = (int)std::max<size_t>(2, budget / per_vec);
       int w = std::min(128, max_vec / 2);
