@@ -121,3 +121,10 @@ def test_planner_c3_scale_stats():
     st = plan.stats()
     assert st["left_updates"] + st["right_updates"] < 0.4 * w.psum.n_terms
     assert 10 <= st["meet_bond"] <= 40
+
+
+def test_autotune_table_host_only():
+    """The tuning table is host state: empty after a reset, without a GPU."""
+    from paper_2303_03681_amd import binding
+    binding.autotune_reset()
+    assert binding.autotune_table() == []
