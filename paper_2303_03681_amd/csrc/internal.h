@@ -206,8 +206,9 @@ hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr,
 hipError_t launch_root_copy(const double2* src, void* dst, size_t count, int elem_bytes, hipStream_t s);
 hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,
                         hipStream_t s);
-hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles,
-                       int elem_bytes, hipStream_t s);
+int gram_splits(int max_kdim);  // K splits of the closing-trace tiles
+hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles, int elem_bytes,
+                       double* part, int splits, hipStream_t s);
 hipError_t launch_rows(const double* per_term, const int64_t* row_ptr, const int64_t* cols, const double* vals,
                        int64_t n_rows, double* out, hipStream_t s);
 hipError_t launch_gather(const double* g, const int64_t* gidx, const double2* nrm, double* per_term,

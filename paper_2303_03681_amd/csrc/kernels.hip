@@ -1330,14 +1330,95 @@ struct GramTileP {
   }
 };
 
-hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles,
-                       int elem_bytes, hipStream_t s) {
-  if (elem_bytes == 16) {
-    GramTileP<double2> p{items_dev, tiles_dev};
+// Split-K form: item i = split * n_tiles + tile sums the K range of its split
+// (K / splits rounded up to 16) into part[i] (64 x 64, row-major); gram_reduce
+// then adds the splits in a fixed order, so the result does not depend on
+// scheduling.  Long traces (K = D^2 up to 262144) are split so that a
+// launch has enough workgroups to fill the chip.
+template <typename C2>
+struct GramSplitP {
+  using T = double;
+  struct Ctx {
+    const void* const* lptr;
+    const void* const* rptr;
+    double* part;
+    int m, n, k0, k;
+  };
+  using RowA = const C2*;
+  using ColB = const C2*;
+  static constexpr bool A_CONTIG_K = true, B_CONTIG_N = false, REAL_ONLY = true;
+  const GramItem* items;
+  const GramTile* tiles;
+  double* part;
+  int n_tiles, splits;
+  __device__ Ctx context(int i) const {
+    const int tile = i % n_tiles, sp = i / n_tiles;
+    const GramTile t = tiles[tile];
+    const GramItem b = items[t.item];
+    const int chunk = ((b.kdim + splits - 1) / splits + 15) & ~15;
+    const int k0 = min(b.kdim, sp * chunk);
+    const int k1 = min(b.kdim, k0 + chunk);
+    return Ctx{b.lptr + t.r0, b.rptr + t.c0, part + (size_t)i * 4096, min(64, b.nl - t.r0),
+               min(64, b.nr - t.c0), k0, k1 - k0};
+  }
+  __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
+    M = c.m;
+    N = c.n;
+    K = c.k;
+  }
+  __device__ static RowA rowA(const Ctx& c, int i) { return (const C2*)c.lptr[i] + c.k0; }
+  __device__ static ColB colB(const Ctx& c, int j) { return (const C2*)c.rptr[j] + c.k0; }
+  __device__ static double2 loadA(const Ctx&, RowA r, int, int k) {
+    const C2 v = r[k];
+    return make_double2((double)v.x, (double)v.y);
+  }
+  __device__ static double2 loadB(const Ctx&, ColB b, int k, int) {
+    const C2 v = b[k];
+    return make_double2((double)v.x, (double)v.y);
+  }
+  __device__ static void store(const Ctx& c, int i, int j, double re, double) { c.part[i * 64 + j] = re; }
+};
+
+__global__ void gram_reduce_kernel(const GramItem* items, const GramTile* tiles, const double* part,
+                                   int n_tiles, int splits) {
+  const int tile = blockIdx.x;
+  const GramTile t = tiles[tile];
+  const GramItem b = items[t.item];
+  const int m = min(64, b.nl - t.r0), n = min(64, b.nr - t.c0);
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+    const int i = e >> 6, j = e & 63;
+    if (i >= m || j >= n) continue;
+    double acc = 0.0;
+    for (int sp = 0; sp < splits; ++sp) acc += part[((size_t)sp * n_tiles + tile) * 4096 + e];
+    b.g[(size_t)(t.r0 + i) * b.nr + t.c0 + j] = acc;
+  }
+}
+
+int gram_splits(int max_kdim) { return max_kdim >= 32768 ? 8 : (max_kdim >= 8192 ? 4 : 1); }
+
+hipError_t launch_gram(const GramItem* items_dev, const GramTile* tiles_dev, int n_tiles, int elem_bytes,
+                       double* part, int splits, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (splits <= 1 || !part) {
+    if (elem_bytes == 16) {
+      GramTileP<double2> p{items_dev, tiles_dev};
+      return launch_cgemm<64, 64, 16>(p, n_tiles, 64, 64, s);
+    }
+    GramTileP<float2> p{items_dev, tiles_dev};
     return launch_cgemm<64, 64, 16>(p, n_tiles, 64, 64, s);
   }
-  GramTileP<float2> p{items_dev, tiles_dev};
-  return launch_cgemm<64, 64, 16>(p, n_tiles, 64, 64, s);
+  hipError_t e;
+  if (elem_bytes == 16) {
+    GramSplitP<double2> p{items_dev, tiles_dev, part, n_tiles, splits};
+    e = launch_cgemm<64, 64, 16>(p, n_tiles * splits, 64, 64, s);
+  } else {
+    GramSplitP<float2> p{items_dev, tiles_dev, part, n_tiles, splits};
+    e = launch_cgemm<64, 64, 16>(p, n_tiles * splits, 64, 64, s);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n_tiles), dim3(256), 0, s, items_dev, tiles_dev, part, n_tiles,
+                     splits);
+  return hipGetLastError();
 }
 
 // <P_k> = closing trace / <psi|psi> (nrm null: unit norm)

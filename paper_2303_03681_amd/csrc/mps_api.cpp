@@ -85,6 +85,9 @@ struct ExpectSetup {
   size_t desc_bytes = 0;
   double* gbuf = nullptr;      // closing traces
   size_t gbuf_count = 0;
+  double* gpart = nullptr;     // split-K partial tiles of the closing traces
+  size_t gpart_count = 0;
+  int gram_split = 1;
   double* per_term = nullptr;
   double* coeffs = nullptr;
   int64_t* gidx = nullptr;
@@ -1135,6 +1138,19 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
     rp_off[g] = put(rptrs[g].data(), rptrs[g].size() * sizeof(void*));
   }
   ex.gram_items = (int)gram.size();
+  int max_kdim = 0;
+  for (const GramItem& gi : gram) max_kdim = std::max(max_kdim, gi.kdim);
+  ex.gram_split = gram_splits(max_kdim);
+  if (ex.gram_split > 1) {
+    const size_t need = (size_t)ex.gram_split * tiles.size() * 4096;
+    if (need > ex.gpart_count || !ex.gpart) {
+      dfree(h, ex.gpart);
+      ex.gpart = nullptr;
+      ex.gpart_count = 0;
+      if ((st = dalloc_t(h, &ex.gpart, std::max<size_t>(need, 1))) != MPS_OK) return st;
+      ex.gpart_count = need;
+    }
+  }
   ex.gram_off = put(nullptr, gram.size() * sizeof(GramItem));
   ex.gram_tiles = (int)tiles.size();
   ex.tiles_off = put(tiles.data(), tiles.size() * sizeof(GramTile));
@@ -1393,7 +1409,8 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
     const bool timed = h->timing && !capturing;
     if (timed && (s2 = timed_begin(h, h->ev_close, h->ev_close_used, b, e)) != MPS_OK) return s2;
     HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off),
-                           (const GramTile*)((char*)ex.desc + ex.tiles_off), ex.gram_tiles, el,
+                           (const GramTile*)((char*)ex.desc + ex.tiles_off), ex.gram_tiles, el, ex.gpart,
+                           ex.gram_split,
                            h->stream));
     if (timed) {
       HIP_TRY(h, hipEventRecord(e, h->stream));
