@@ -53,3 +53,34 @@ def test_uccsd_gradient_vs_dense_finite_differences(gpu_lib):
     assert all(b < a for a, b in zip(energies, energies[1:]))
     assert min(energies) >= e_exact - 1e-9
     gr.close()
+
+
+def test_mps_copy_contract(gpu_lib):
+    """mps_copy takes the source state exactly (energies, norm, bond dims,
+    discarded weight) and refuses handles of other shapes, leaving the target
+    unchanged."""
+    from paper_2303_03681_amd import binding
+    w = build_config(1)
+    n = w.n_qubits
+    plan = binding.PauliSum(w.psum.codes, w.psum.coeffs)
+    src = binding.Mps(n, 16, 1e-14, bits=w.bits)
+    from workloads import pack_gates
+    q0, q1, u = pack_gates(w.gates)
+    src.apply_gates(q0[:300], q1[:300], u[:300])
+    dst = binding.Mps(n, 16, 1e-14)
+    dst.copy_from(src)
+    assert list(dst.bond_dims()) == list(src.bond_dims())
+    assert dst.expect(plan) == src.expect(plan)
+    assert dst.norm() == src.norm() and dst.discarded_weight() == src.discarded_weight()
+    # continuing both with the same gates keeps them identical; the source is untouched by the copy
+    for m in (src, dst):
+        m.apply_gates(q0[300:], q1[300:], u[300:])
+    assert dst.expect(plan) == src.expect(plan)
+    other = binding.Mps(n, 8, 1e-14)
+    before = other.expect(plan)
+    with pytest.raises(binding.MpsError) as ex:
+        other.copy_from(src)
+    assert ex.value.name == "MPS_ERR_ARG"
+    assert other.expect(plan) == before
+    with pytest.raises(binding.MpsError):
+        binding.Mps(n + 2, 16, 1e-14).copy_from(src)
