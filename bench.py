@@ -233,9 +233,8 @@ def main():
                          "size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus "
-              f"{args.gpus}); the string set would shard across GPUs as described in DESIGN.md.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no multi-GPU "
+              f"path; the Pauli strings would shard across GPUs by trie subtree.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -127,7 +127,7 @@ def load():
         pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                           "(run __graft_entry__.build() or python -m paper_2303_03681_amd.build)")
+                           "(run python -m paper_2303_03681_amd.build)")
     lib = C.CDLL(LIB_PATH)
     for name, args in _SIGS.items():
         fn = getattr(lib, name)

@@ -1,8 +1,9 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
 identical seeded inputs.  Tolerances: c128 energies within 1e-9 of the
 oracle (absolute, Hartree), per-string values within 1e-10; c64 energies
-within 1e-6 (derived in the design doc from FP32 rounding over the transfer
-chains); singular values within 1e-12 relative to the largest."""
+within 1e-6 (FP32 rounding, about 6e-8 relative per product, accumulated
+over chains of up to a few dozen transfer products); singular values within
+1e-12 relative to the largest."""
 
 import math
 
