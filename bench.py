@@ -189,12 +189,32 @@ def serving_sample(n_fragments: int, prec: str) -> dict:
     alone = srv.run([Request(0, big.fid, 0, 0.0)], timeout_s=600).requests[0]
     srv.close()
     e_mix = next(r.energy for r in rep.requests if r.fid == big.fid)
+    # the serving expectation in the requested precision against complex128 on
+    # the largest fragment's state (same gates): strings/s and |dE|
+    from paper_2303_03681_amd import binding
+    m = binding.Mps(big.n_qubits, big.max_bond, big.cutoff, bits=big.bits)
+    m.apply_gates(*big.updates[0])
+    plan = binding.PauliSum(big.codes, big.coeffs)
+    cmp = {}
+    for pr in dict.fromkeys((prec, "c128")):
+        m.expect(plan, pr)  # setup
+        t1 = time.perf_counter()
+        for _ in range(5):
+            e_pr = m.expect(plan, pr)
+        dt = (time.perf_counter() - t1) / 5
+        cmp[pr] = {"expect_ms": 1e3 * dt, "strings_per_s": big.codes.shape[0] / dt, "energy": e_pr}
+    for pr in cmp:
+        cmp[pr]["abs_dE_vs_c128"] = abs(cmp[pr]["energy"] - cmp["c128"]["energy"])
+    m.close()
+    plan.close()
     out.update({
         "workload": (f"{n_fragments} fragments, qubits in {list(qubits)}, D in {list(bonds)}, "
                      "windowed UCCSD, cutoff 1e-10, Poisson arrivals 200/s, one update each"),
         "gates_per_request_mean": float(np.mean([len(f.updates[0][0]) for f in frags])),
         "alone_vs_mix": {"fragment": big.fid, "latency_alone_s": alone.latency,
                          "abs_dE": abs(alone.energy - e_mix)},
+        "expect_precision_vs_c128": {"fragment": big.fid, "n_qubits": big.n_qubits, "max_bond": big.max_bond,
+                                     "strings": int(big.codes.shape[0]), **cmp},
     })
     return out
 
