@@ -259,7 +259,7 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
  * table entry -- class = (device, precision, GEMM half, D_l, D_r,
  * ceil(log2 of the items in the launch)) -- runs that launch with every tile
  * shape (BM x BN x BK in {64x64x16, 32x32x16, 128x64x16, 64x128x16,
- * 64x64x32, 32x64x16}) twice, timed with HIP events, and records the
+ * 64x64x32, 32x64x16, 128x128x16, 128x128x8}) twice, timed with HIP events, and records the
  * fastest; later launches of the class use it.  The table is process-wide
  * per device and shared by all handles.  Every tile shape gives bitwise
  * identical results (each output element accumulates its K range in the
@@ -281,14 +281,14 @@ mps_status mps_set_autotune(mps_handle h, int32_t enabled);
  * Results are bitwise those of the eager path.  Disabling frees the graph. */
 mps_status mps_set_graphs(mps_handle h, int32_t enabled);
 
-/* Use tile shape `tile` (0..5, in the order listed for mps_set_autotune) for
+/* Use tile shape `tile` (0..7, in the order listed for mps_set_autotune) for
  * every c128/c64 environment GEMM of this handle, overriding the table;
  * -1 (the default) returns to the table or the default tile 0.  For
  * comparisons and tests.  Other values are MPS_ERR_ARG. */
 mps_status mps_set_env_tile(mps_handle h, int32_t tile);
 
 /* The tuning table as text, one line per launch class:
- *   device precision half D_l D_r bucket tile BMxBNxBK ms_0 .. ms_5
+ *   device precision half D_l D_r bucket tile BMxBNxBK ms_0 .. ms_7
  * (half 1: X = L [A^0|A^1], half 2: L' = sum A^+ X; ms_t the faster of two
  * runs of tile t).  *len (may be NULL) receives the bytes needed including
  * the terminating NUL; buf may be NULL to query the length; a non-NULL buf

@@ -315,7 +315,7 @@ class Mps:
         _check(_lib.mps_set_graphs(self._h, 1 if on else 0))
 
     def set_env_tile(self, tile: int = -1):
-        """Force one environment GEMM tile shape (0..5); -1 restores the default."""
+        """Force one environment GEMM tile shape (0..7); -1 restores the default."""
         _check(_lib.mps_set_env_tile(self._h, int(tile)))
 
     def set_timing(self, on: bool = True):

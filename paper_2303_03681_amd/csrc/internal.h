@@ -185,9 +185,9 @@ hipError_t launch_fill_ident(double2* dst, int d, hipStream_t s);
 
 // environment products: c128 on FP64 MFMA, c64 on FP32 MFMA, with a choice of
 // workgroup tile shapes (BM, BN, BK); index 0 is the default
-constexpr int kEnvTiles = 6;
-constexpr int kEnvTileShape[kEnvTiles][3] = {{64, 64, 16}, {32, 32, 16}, {128, 64, 16},
-                                             {64, 128, 16}, {64, 64, 32}, {32, 64, 16}};
+constexpr int kEnvTiles = 8;
+constexpr int kEnvTileShape[kEnvTiles][3] = {{64, 64, 16},  {32, 32, 16},   {128, 64, 16}, {64, 128, 16},
+                                             {64, 64, 32},  {32, 64, 16},   {128, 128, 16}, {128, 128, 8}};
 hipError_t launch_env_gemm1_c128(const EnvParent<double2>* items, int count, const double2* site,
                                  int dl, int dr, hipStream_t s, int tile = 0);
 hipError_t launch_env_gemm2_c128(const EnvChild<double2>* items, int count, const double2* site,

@@ -1163,10 +1163,12 @@ hipError_t launch_env_tile(const P& p, int tile, int count, int m, int n, hipStr
     case 3: return launch_cgemm<64, 128, 16>(p, count, m, n, s);
     case 4: return launch_cgemm<64, 64, 32>(p, count, m, n, s);
     case 5: return launch_cgemm<32, 64, 16>(p, count, m, n, s);
+    case 6: return launch_cgemm<128, 128, 16>(p, count, m, n, s);
+    case 7: return launch_cgemm<128, 128, 8>(p, count, m, n, s);
     default: return hipErrorInvalidValue;
   }
 }
-static_assert(kEnvTiles == 6, "launch_env_tile covers every tile shape");
+static_assert(kEnvTiles == 8, "launch_env_tile covers every tile shape");
 
 hipError_t launch_env_gemm1_c128(const EnvParent<double2>* items, int count, const double2* site,
                                  int dl, int dr, hipStream_t s, int tile) {

@@ -27,13 +27,13 @@ def test_every_tile_shape_bitwise_equal(gpu_lib):
     m, plan = _state(binding)
     for prec in ("c128", "c64"):
         e0, p0 = m.expect(plan, prec, per_term=True)
-        for t in range(6):
+        for t in range(8):
             m.set_env_tile(t)
             e, p = m.expect(plan, prec, per_term=True)
             assert np.array_equal(p, p0) and e == e0, (prec, t)
         m.set_env_tile(-1)
     with pytest.raises(binding.MpsError):
-        m.set_env_tile(6)
+        m.set_env_tile(8)
 
 
 def test_autotune_table_and_results(gpu_lib):
@@ -50,10 +50,11 @@ def test_autotune_table_and_results(gpu_lib):
     rows = binding.autotune_table()
     assert {r["prec"] for r in rows} == {"c128", "c64"}
     assert {r["half"] for r in rows} == {1, 2}
-    shapes = ["64x64x16", "32x32x16", "128x64x16", "64x128x16", "64x64x32", "32x64x16"]
+    shapes = ["64x64x16", "32x32x16", "128x64x16", "64x128x16", "64x64x32", "32x64x16", "128x128x16",
+              "128x128x8"]
     for r in rows:
-        assert 0 <= r["tile"] < 6 and r["shape"] == shapes[r["tile"]]
-        assert len(r["ms"]) == 6 and all(x > 0 for x in r["ms"])
+        assert 0 <= r["tile"] < 8 and r["shape"] == shapes[r["tile"]]
+        assert len(r["ms"]) == 8 and all(x > 0 for x in r["ms"])
         assert r["ms"][r["tile"]] == min(r["ms"])
     # a second handle of the same shapes finds every class in the table
     m2, plan2 = _state(binding)
