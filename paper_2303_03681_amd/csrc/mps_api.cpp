@@ -142,6 +142,7 @@ struct mps_state {
   std::vector<double*> lam[2];
   std::vector<int> lam_cur;
   bool canonical = true;  // exact canonical form: right-orthonormal sites, Schmidt lambdas
+  uint64_t version = 0;    // bumped by every change of the state (gates, canonical form, reset, import, copy)
   // identity environments from both boundaries (FP64), the trie roots when the
   // sites are not in exact canonical form: left L_b (slot b), right R_b^T
   double2* d_lchain = nullptr;
@@ -150,6 +151,8 @@ struct mps_state {
   double2* d_chaintr = nullptr; // one site tensor, transposed, for the right chain
   void* d_chaindesc = nullptr;
   std::vector<size_t> chain_off;
+  uint64_t chain_version = ~0ull;  // state version the boundary environments were computed for
+  int chain_rmin = 1 << 30;        // ... and the lowest bond of the right chain
   double norm = 1.0;
   double discarded = 0.0;
   // device helpers
@@ -652,6 +655,7 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
     h->discarded += disc[b];
   }
   h->canonical = false;
+  ++h->version;
   return MPS_OK;
 }
 
@@ -752,6 +756,7 @@ mps_status canonicalize_impl(mps_state* h) {
   }
   if ((st = sync(h)) != MPS_OK) return st;
   h->canonical = true;
+  ++h->version;
   h->tm.canon_ms += now_ms() - t0;
   return MPS_OK;
 }
@@ -762,7 +767,8 @@ mps_status canonicalize_impl(mps_state* h) {
 // pass, R_b^T = sum_s (B_b^{sT})^+ R_{b+1}^T B_b^{sT} for b >= rmin.  They
 // replace diag(lambda^2) and the identity (Eqs. expec1, rc) as trie roots
 // when the sites are not in exact canonical form.  Slots and descriptors are
-// laid out once by bond capacity.
+// laid out once by bond capacity; the chains are recomputed only after the
+// state changed (e.g. several Pauli sums, or chunks of one, on one state).
 mps_status identity_chains(mps_state* h, int rmin) {
   const int n = h->n;
   mps_status st;
@@ -776,17 +782,21 @@ mps_status identity_chains(mps_state* h, int rmin) {
       tot += (size_t)h->cap[b] * h->cap[b];
       if (b < n) xmax = std::max(xmax, (size_t)h->cap[b] * 2 * h->cap[b + 1]);
     }
-    double2 *lc = nullptr, *rc = nullptr, *cx = nullptr, *ctr = nullptr;
+    // cx: GEMM1 output of the left chain, cxr: of the right chain (the chains
+    // may run concurrently), ctr: the transposed site of the right chain
+    double2 *lc = nullptr, *rc = nullptr, *cx = nullptr, *cxr = nullptr, *ctr = nullptr;
     void* desc = nullptr;
     auto undo = [&]() {
       dfree(h, lc);
       dfree(h, rc);
       dfree(h, cx);
+      dfree(h, cxr);
       dfree(h, ctr);
       dfree(h, desc);
     };
     if ((st = dalloc_t(h, &lc, tot)) != MPS_OK || (st = dalloc_t(h, &rc, tot)) != MPS_OK ||
-        (st = dalloc_t(h, &cx, xmax)) != MPS_OK || (st = dalloc_t(h, &ctr, xmax)) != MPS_OK ||
+        (st = dalloc_t(h, &cx, xmax)) != MPS_OK || (st = dalloc_t(h, &cxr, xmax)) != MPS_OK ||
+        (st = dalloc_t(h, &ctr, xmax)) != MPS_OK ||
         (st = dalloc(h, &desc, 2 * (sizeof(P) + sizeof(Ch)) * n)) != MPS_OK) {
       undo();
       return st;
@@ -800,8 +810,8 @@ mps_status identity_chains(mps_state* h, int rmin) {
     for (int q = 0; q < n; ++q) {
       lp[q] = P{lc + off[q], cx};
       lch[q] = Ch{cx, lc + off[q + 1], 0};
-      rp[q] = P{rc + off[q + 1], cx};
-      rch[q] = Ch{cx, rc + off[q], 0};
+      rp[q] = P{rc + off[q + 1], cxr};
+      rch[q] = Ch{cxr, rc + off[q], 0};
     }
     const double2 one = make_double2(1.0, 0.0);
     hipError_t e = hipMemcpy(desc, host.data(), host.size(), hipMemcpyHostToDevice);
@@ -818,20 +828,40 @@ mps_status identity_chains(mps_state* h, int rmin) {
     h->d_chaindesc = desc;
     h->chain_off = off;
   }
+  if (h->chain_version == h->version && h->chain_rmin <= rmin) return MPS_OK;  // still current
   const P* lp = (const P*)h->d_chaindesc;
   const Ch* lch = (const Ch*)(lp + n);
   const P* rp = (const P*)(lch + n);
   const Ch* rch = (const Ch*)(rp + n);
+  // the two chains are independent: the right one runs on the second stream;
+  // one item per launch, so the small 32 x 32 tile (four times the
+  // workgroups of the default) once the bonds are large
+  const bool split = n >= 8;
+  hipStream_t rs = h->stream;
+  if (split) {
+    if ((st = ensure_side(h)) != MPS_OK) return st;
+    HIP_TRY(h, hipEventRecord(h->ev_fork, h->stream));
+    HIP_TRY(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    rs = h->side;
+  }
+  auto tile = [&](int a, int b) { return std::max(a, b) >= 128 ? 1 : 0; };
   for (int q = 0; q < n; ++q) {
-    HIP_TRY(h, launch_env_gemm1_c128(lp + q, 1, h->cur(q), h->dims[q], h->dims[q + 1], h->stream));
-    HIP_TRY(h, launch_env_gemm2_c128(lch + q, 1, h->cur(q), h->dims[q], h->dims[q + 1], h->stream));
+    const int t = tile(h->dims[q], h->dims[q + 1]);
+    HIP_TRY(h, launch_env_gemm1_c128(lp + q, 1, h->cur(q), h->dims[q], h->dims[q + 1], h->stream, t));
+    HIP_TRY(h, launch_env_gemm2_c128(lch + q, 1, h->cur(q), h->dims[q], h->dims[q + 1], h->stream, t));
   }
   for (int q = n - 1; q >= rmin; --q) {
-    HIP_TRY(h, launch_site_prepare(h->cur(q), nullptr, h->d_chaintr, h->dims[q], h->dims[q + 1], 16,
-                                   h->stream));
-    HIP_TRY(h, launch_env_gemm1_c128(rp + q, 1, h->d_chaintr, h->dims[q + 1], h->dims[q], h->stream));
-    HIP_TRY(h, launch_env_gemm2_c128(rch + q, 1, h->d_chaintr, h->dims[q + 1], h->dims[q], h->stream));
+    const int t = tile(h->dims[q], h->dims[q + 1]);
+    HIP_TRY(h, launch_site_prepare(h->cur(q), nullptr, h->d_chaintr, h->dims[q], h->dims[q + 1], 16, rs));
+    HIP_TRY(h, launch_env_gemm1_c128(rp + q, 1, h->d_chaintr, h->dims[q + 1], h->dims[q], rs, t));
+    HIP_TRY(h, launch_env_gemm2_c128(rch + q, 1, h->d_chaintr, h->dims[q + 1], h->dims[q], rs, t));
   }
+  if (split) {
+    HIP_TRY(h, hipEventRecord(h->ev_join, h->side));
+    HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+  }
+  h->chain_version = h->version;
+  h->chain_rmin = rmin;
   return MPS_OK;
 }
 
@@ -1694,6 +1724,7 @@ mps_status mps_reset(mps_handle h, const uint8_t* bits) {
   HIP_TRY(h, launch_init_product(h->d_site_ptrs, h->d_lam_ptrs, h->d_bits, n, h->stream));
   if ((st = sync(h)) != MPS_OK) return st;
   h->canonical = true;
+  ++h->version;
   h->norm = 1.0;
   h->discarded = 0.0;
   return MPS_OK;
@@ -1762,6 +1793,7 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
         else
           HIP_TRY(h, launch_gate1q(h->cur(q), ug, h->dims[q] * h->dims[q + 1], h->stream));
         h->canonical = false;
+        ++h->version;
         ++i;
         if (!h->fused_active) done = i;
         continue;
@@ -1783,6 +1815,7 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
           if ((st = fused_launch(h, qs[b], h->d_gates + (size_t)gi[b] * 16, gi[b])) != MPS_OK)
             return finish(st);
         h->canonical = false;
+        ++h->version;
         i = j;
         continue;
       }
@@ -1890,7 +1923,10 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const 
     if ((st = fused_flush(h, &bad, &code)) != MPS_OK) return st;
     const int64_t done = bad >= 0 ? bad : n_gates[i];
     if (n_done) n_done[i] = done;
-    if (done > 0) h->canonical = false;
+    if (done > 0) {
+      h->canonical = false;
+      ++h->version;
+    }
     h->tm.gates_ms += dt;
     if (bad >= 0 && first == MPS_OK) {
       first = code == 2 ? MPS_ERR_NOCONV : MPS_ERR_NONFINITE;
@@ -2061,6 +2097,7 @@ mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, cons
   h->dims[q] = dl;
   h->dims[q + 1] = dr;
   h->canonical = true;
+  ++h->version;
   return MPS_OK;
 }
 
@@ -2176,6 +2213,7 @@ mps_status mps_copy(mps_handle dst, mps_handle src) {
   if ((st = sync(dst)) != MPS_OK) return st;
   dst->dims = src->dims;
   dst->canonical = src->canonical;
+  ++dst->version;
   dst->norm = src->norm;
   dst->discarded = src->discarded;
   return MPS_OK;

@@ -14,7 +14,7 @@ from oracle import MpsOracle, dense_apply_gates, dense_energy, dense_expect_paul
     dense_product_state
 from workloads import brickwork_gates, build_config, fuse_gates, hf_bits, jw_hamiltonian, \
     pack_gates, random_integrals, workload_rng
-from workloads.circuits import gate_cnot
+from workloads.circuits import Gate, gate_cnot
 
 pytestmark = pytest.mark.gpu
 
@@ -414,3 +414,35 @@ def test_noconv_reports_gates_applied(gpu_lib, fused):
     assert list(m.bond_dims()) == list(ref.bond_dims())
     plan = binding.PauliSum(np.eye(n, dtype=np.uint8) * 3, np.ones(n))
     assert abs(m.expect(plan) - ref.expect(plan)) < 1e-12
+
+
+def test_boundary_environments_follow_state_changes(gpu_lib):
+    """The boundary environments are reused while the state is unchanged and
+    recomputed after every change: gates, copies and canonicalisation."""
+    from paper_2303_03681_amd import binding
+    w = build_config(1)
+    n = w.n_qubits
+    plan = binding.PauliSum(w.psum.codes, w.psum.coeffs)
+    q0, q1, u = pack_gates(w.gates)
+    half = len(q0) // 2
+
+    def dense_e(gates):
+        return dense_energy(dense_apply_gates(dense_product_state(w.bits), gates), w.psum.codes, w.psum.coeffs)
+    m = binding.Mps(n, 16, 1e-14, bits=w.bits)
+    m.apply_gates(q0[:half], q1[:half], u[:half])
+    e1 = dense_e(w.gates[:half])
+    assert abs(m.expect(plan) - e1) < 1e-10
+    assert abs(m.expect(plan, "c64") - e1) < 1e-5  # same state, environments reused
+    m.apply_gates(q0[half:], q1[half:], u[half:])
+    e2 = dense_e(w.gates)
+    assert abs(m.expect(plan) - e2) < 1e-10
+    other = binding.Mps(n, 16, 1e-14, bits=w.bits)
+    other.apply_gates(q0[:10], q1[:10], u[:10])
+    other.expect(plan)  # environments of another state
+    other.copy_from(m)
+    assert abs(other.expect(plan) - e2) < 1e-10
+    m.canonicalize()
+    assert abs(m.expect(plan) - e2) < 1e-10
+    x = np.array([[0, 1], [1, 0]], dtype=complex)
+    m.apply_gate(3, -1, x)
+    assert abs(m.expect(plan) - dense_e(list(w.gates) + [Gate(3, -1, x)])) < 1e-10
