@@ -142,6 +142,12 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* handles,
  * path.  For comparisons and tests. */
 mps_status mps_set_fused_gates(mps_handle h, int32_t enabled);
 
+/* Allow (enabled != 0, the default) or forbid splitting the batched gate
+ * SVDs (Algorithm 1 rounds of the register kernels) of one brickwork layer
+ * into two groups on two streams.  Each matrix sees the same rotation
+ * rounds either way; for comparisons and tests. */
+mps_status mps_set_jacobi_split(mps_handle h, int32_t enabled);
+
 /* Copy the state of src into dst (site tensors, lambdas, bond dimensions,
  * canonical flag, norm, discarded weight), device to device on dst's
  * stream after src's stream has drained; returns when the copy is complete,

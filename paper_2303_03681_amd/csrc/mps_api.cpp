@@ -204,6 +204,10 @@ struct mps_state {
   // beside the multi-launch rounds of the large gates of the same batch
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // second group of the register Jacobi items (see run_jacobi)
+  hipStream_t jside = nullptr;
+  hipEvent_t ev_jfork = nullptr, ev_jjoin = nullptr;
+  bool jacobi_split = true;
   mps_timing tm{};
 
   double2* cur(int q) { return site[site_cur[q]][q]; }
@@ -306,6 +310,14 @@ mps_status ensure_side(mps_state* h) {
   return MPS_OK;
 }
 
+mps_status ensure_jside(mps_state* h) {
+  if (h->jside) return MPS_OK;
+  HIP_TRY(h, hipEventCreateWithFlags(&h->ev_jfork, hipEventDisableTiming));
+  HIP_TRY(h, hipEventCreateWithFlags(&h->ev_jjoin, hipEventDisableTiming));
+  HIP_TRY(h, hipStreamCreateWithFlags(&h->jside, hipStreamNonBlocking));
+  return MPS_OK;
+}
+
 mps_status ensure_desc(mps_state* h, size_t bytes) {
   if (bytes <= h->desc_bytes) return MPS_OK;
   if (h->d_desc) {
@@ -369,6 +381,7 @@ constexpr int kRegBlock = 8;     // vectors per block of the register kernels (o
 constexpr int kRegMaxLen = 512;  // longest vector the register kernels hold
 constexpr int kSmallMax = 128;   // rows and row length of the one-workgroup register kernel
 constexpr size_t kWideLdsBytes = (size_t)kRegBlock * 2 * kRegMaxLen * sizeof(double2);  // one block in LDS
+constexpr int64_t kSplitWorkgroups = 256;  // register rounds split over two streams above this size
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
@@ -435,6 +448,44 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
       return fail(MPS_ERR_STATE, "internal: Jacobi rotation counters not laid out [sweep][item]");
   JacobiPlanHost jp;
   plan_jacobi(all, jp);
+  // Register items in two groups on two streams.  One round of a large
+  // batch launches more waves than the chip holds at once (two per SIMD at
+  // this kernel's register use), so a launch runs as a full generation of
+  // waves plus a sparse second one; with the items dealt (largest first,
+  // alternately) into two groups whose rounds are queued on two streams,
+  // the waves of one group's round fill the slots the other's leaves idle.
+  // Every item still sees the same rounds in the same order as on one
+  // stream.
+  int reg_a = (int)jp.reg.size();
+  int pairs_a = jp.reg_pairs, pairs_b = 0, rounds_a = jp.reg_rounds, rounds_b = 0;
+  int maxm_a = jp.reg_max_m, maxm_b = 0;
+  {
+    int64_t wgs = 0;
+    for (const JacItem& it : jp.reg) wgs += it.nb / 2;
+    if (h->jacobi_split && jp.reg.size() >= 4 && wgs > kSplitWorkgroups) {
+      std::vector<JacItem> srt = jp.reg;
+      std::stable_sort(srt.begin(), srt.end(), [](const JacItem& a, const JacItem& b) {
+        return (int64_t)a.n * a.m > (int64_t)b.n * b.m;
+      });
+      std::vector<JacItem> ga, gb;
+      for (size_t i = 0; i < srt.size(); ++i) (i & 1 ? gb : ga).push_back(srt[i]);
+      reg_a = (int)ga.size();
+      pairs_a = pairs_b = rounds_a = rounds_b = maxm_a = maxm_b = 0;
+      for (const JacItem& it : ga) {
+        pairs_a = std::max(pairs_a, it.nb / 2);
+        rounds_a = std::max(rounds_a, it.nb - 1);
+        maxm_a = std::max(maxm_a, it.m);
+      }
+      for (const JacItem& it : gb) {
+        pairs_b = std::max(pairs_b, it.nb / 2);
+        rounds_b = std::max(rounds_b, it.nb - 1);
+        maxm_b = std::max(maxm_b, it.m);
+      }
+      jp.reg = ga;
+      jp.reg.insert(jp.reg.end(), gb.begin(), gb.end());
+    }
+  }
+  const int reg_b = (int)jp.reg.size() - reg_a;
   const size_t bytes =
       (jp.small.size() + jp.single.size() + jp.reg.size() + jp.block.size() + jp.wide.size()) *
       sizeof(JacItem);
@@ -486,6 +537,21 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   for (const JacItem& b : jp.wide) is_multi[b.rot - all[0].rot] = 1;
   const int nmulti = nmulti_items;
   const bool timed = h->timing && nmulti > 0;
+  if (reg_b > 0) {
+    if ((st = ensure_jside(h)) != MPS_OK) return st;
+    HIP_TRY(h, hipEventRecord(h->ev_jfork, h->stream));
+    HIP_TRY(h, hipStreamWaitEvent(h->jside, h->ev_jfork, 0));
+  }
+  // the handle's stream waits for the second group after every sweep (also
+  // on an early return)
+  struct JoinB {
+    mps_state* h;
+    bool on;
+    ~JoinB() {
+      if (on && hipEventRecord(h->ev_jjoin, h->jside) == hipSuccess)
+        (void)hipStreamWaitEvent(h->stream, h->ev_jjoin, 0);
+    }
+  } join_b{h, false};
   if (timed) {
     for (hipEvent_t& ev : h->ev_jac)
       if (!ev) HIP_TRY(h, hipEventCreate(&ev));
@@ -498,15 +564,23 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
     for (int sw = 0; sw < h->max_sweeps && done < nmulti; ++sw) {
       h->tm.jacobi_batch_sweeps += 1;
       for (int r = 0; r < rounds; ++r) {
-        if (!jp.reg.empty() && r < jp.reg_rounds)
-          HIP_TRY(h, launch_jacobi_reg(d_reg, (int)jp.reg.size(), jp.reg_pairs, r, sw, kEpsScale,
-                                       jp.reg_max_m, h->stream));
+        if (reg_a > 0 && r < rounds_a)
+          HIP_TRY(h, launch_jacobi_reg(d_reg, reg_a, pairs_a, r, sw, kEpsScale, maxm_a, h->stream));
+        if (reg_b > 0 && r < rounds_b) {
+          join_b.on = true;
+          HIP_TRY(h, launch_jacobi_reg(d_reg + reg_a, reg_b, pairs_b, r, sw, kEpsScale, maxm_b, h->jside));
+        }
         if (!jp.block.empty() && r < jp.block_rounds)
           HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
                                          kEpsScale, jp.block_lds, h->stream));
         if (!jp.wide.empty() && r < jp.wide_rounds)
           HIP_TRY(h, launch_jacobi_wide(d_wide, (int)jp.wide.size(), jp.wide_pairs, r, sw, kEpsScale,
                                         h->stream));
+      }
+      if (reg_b > 0) {
+        HIP_TRY(h, hipEventRecord(h->ev_jjoin, h->jside));
+        HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_jjoin, 0));
+        join_b.on = false;
       }
       if (sw >= 3 || sw == h->max_sweeps - 1) {
         HIP_TRY(h, hipMemcpyAsync(rot.data(), all[0].rot + (size_t)sw * count, sizeof(int) * count,
@@ -1686,6 +1760,7 @@ mps_status mps_destroy(mps_handle h) {
   if (!h) return MPS_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->side) (void)hipStreamSynchronize(h->side);
+  if (h->jside) (void)hipStreamSynchronize(h->jside);
   drop_graph(h->ex);
   for (auto& a : h->allocs) (void)hipFree(a.first);
   for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
@@ -1694,6 +1769,9 @@ mps_status mps_destroy(mps_handle h) {
   for (hipEvent_t e : h->ev_jac)
     if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->jside) (void)hipStreamDestroy(h->jside);
+  if (h->ev_jfork) (void)hipEventDestroy(h->ev_jfork);
+  if (h->ev_jjoin) (void)hipEventDestroy(h->ev_jjoin);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -2183,6 +2261,13 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
       }
   }
   if (sweeps) *sweeps = swp[0];
+  return MPS_OK;
+}
+
+mps_status mps_set_jacobi_split(mps_handle h, int32_t enabled) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  h->jacobi_split = enabled != 0;
   return MPS_OK;
 }
 
