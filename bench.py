@@ -247,6 +247,8 @@ def main():
                     help="skip the graph-replay and gradient samples (e.g. for kernel profiles)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default environment GEMM tile (no tuning in the warmup)")
+    ap.add_argument("--jacobi-groups", type=int, default=2,
+                    help="streams over which the batched gate SVD rounds are split (1 = none)")
     ap.add_argument("--serving-fragments", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy of known "
@@ -289,6 +291,7 @@ def main():
     m = binding.Mps(w.n_qubits, w.spec.max_bond, w.spec.cutoff, bits=w.bits,
                     stream=stream.cuda_stream)
     m.set_autotune(not args.no_autotune)  # tile tuning happens in the first (warmup) expectation
+    m.set_jacobi_groups(args.jacobi_groups)
 
     def step(prec, verbose=False):
         m.reset(w.bits)
@@ -433,6 +436,7 @@ def main():
                                   if tm["close_ms"] > 0 else 0.0),
                   "gflop_per_step": tm["close_flops"] / K / 1e9},
         "jacobi_sweeps_per_step": tm["jacobi_sweeps"] / K,
+        "jacobi_groups": args.jacobi_groups,
         "jacobi_batch_sweeps_per_step": tm["jacobi_batch_sweeps"] / K,
         "expect_phase_by_precision": precisions,
         "plan": st,

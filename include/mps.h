@@ -142,11 +142,14 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* handles,
  * path.  For comparisons and tests. */
 mps_status mps_set_fused_gates(mps_handle h, int32_t enabled);
 
-/* Allow (enabled != 0, the default) or forbid splitting the batched gate
- * SVDs (Algorithm 1 rounds of the register kernels) of one brickwork layer
- * into two groups on two streams.  Each matrix sees the same rotation
- * rounds either way; for comparisons and tests. */
-mps_status mps_set_jacobi_split(mps_handle h, int32_t enabled);
+/* Number of groups (1..3, default 2) into which the batched gate SVDs of
+ * one brickwork layer are split, each group's Algorithm 1 rounds (register
+ * kernels) queued on a stream of its own so that the rounds of one group
+ * fill the compute units the others leave idle.  Used only when a round
+ * would launch more than 256 workgroups.  Each matrix sees the same
+ * rotation rounds for every group count; 1 turns the split off (for
+ * comparisons and tests).  MPS_ERR_ARG outside 1..3. */
+mps_status mps_set_jacobi_groups(mps_handle h, int32_t groups);
 
 /* Copy the state of src into dst (site tensors, lambdas, bond dimensions,
  * canonical flag, norm, discarded weight), device to device on dst's

@@ -96,7 +96,7 @@ _SIGS = {
     "mps_jacobi_svd": [_I32, _I32, _P, _P, _P, _P],
     "mps_set_timing": [_P, _I32],
     "mps_set_fused_gates": [_P, _I32],
-    "mps_set_jacobi_split": [_P, _I32],
+    "mps_set_jacobi_groups": [_P, _I32],
     "mps_set_autotune": [_P, _I32],
     "mps_autotune_table": [_P, _I64, _P],
     "mps_autotune_reset": [],
@@ -303,9 +303,9 @@ class Mps:
         """Allow or forbid the fused single-gate path of apply_gates."""
         _check(_lib.mps_set_fused_gates(self._h, 1 if on else 0))
 
-    def set_jacobi_split(self, on: bool = True):
-        """Allow or forbid the two-stream split of the batched gate SVD rounds."""
-        _check(_lib.mps_set_jacobi_split(self._h, 1 if on else 0))
+    def set_jacobi_groups(self, groups: int = 2):
+        """Streams (1..3) over which the batched gate SVD rounds are split."""
+        _check(_lib.mps_set_jacobi_groups(self._h, int(groups)))
 
     def set_autotune(self, on: bool = True):
         """Choose the environment GEMM tile shapes by measurement (c128, c64)."""

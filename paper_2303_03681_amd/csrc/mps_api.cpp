@@ -39,6 +39,8 @@ constexpr double kEpsScale = 1.1102230246251565e-16;  // 2^-53: eps = m * 2^-53 
 constexpr double kCanonCutoff = 1e-14;                  // round-off singular values only
 constexpr int kDefaultSweeps = 60;
 constexpr int kMaxBond = 512;                           // finalize handles 2D <= 1024 vectors
+constexpr int kMaxJacobiGroups = 3;      // streams of the batched register Jacobi rounds
+constexpr int kDefaultJacobiGroups = 2;
 
 int cap_dim(int b, int n, int D) {
   const int e = std::min(b, n - b);
@@ -204,10 +206,10 @@ struct mps_state {
   // beside the multi-launch rounds of the large gates of the same batch
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // second group of the register Jacobi items (see run_jacobi)
-  hipStream_t jside = nullptr;
-  hipEvent_t ev_jfork = nullptr, ev_jjoin = nullptr;
-  bool jacobi_split = true;
+  // streams of the register Jacobi item groups after the first (see run_jacobi)
+  hipStream_t jside[kMaxJacobiGroups - 1] = {};
+  hipEvent_t ev_jfork = nullptr, ev_jjoin[kMaxJacobiGroups - 1] = {};
+  int jacobi_groups = kDefaultJacobiGroups;
   mps_timing tm{};
 
   double2* cur(int q) { return site[site_cur[q]][q]; }
@@ -310,11 +312,13 @@ mps_status ensure_side(mps_state* h) {
   return MPS_OK;
 }
 
-mps_status ensure_jside(mps_state* h) {
-  if (h->jside) return MPS_OK;
-  HIP_TRY(h, hipEventCreateWithFlags(&h->ev_jfork, hipEventDisableTiming));
-  HIP_TRY(h, hipEventCreateWithFlags(&h->ev_jjoin, hipEventDisableTiming));
-  HIP_TRY(h, hipStreamCreateWithFlags(&h->jside, hipStreamNonBlocking));
+mps_status ensure_jside(mps_state* h, int groups) {
+  if (!h->ev_jfork) HIP_TRY(h, hipEventCreateWithFlags(&h->ev_jfork, hipEventDisableTiming));
+  for (int g = 0; g + 1 < groups; ++g) {
+    if (h->jside[g]) continue;
+    HIP_TRY(h, hipEventCreateWithFlags(&h->ev_jjoin[g], hipEventDisableTiming));
+    HIP_TRY(h, hipStreamCreateWithFlags(&h->jside[g], hipStreamNonBlocking));
+  }
   return MPS_OK;
 }
 
@@ -381,7 +385,7 @@ constexpr int kRegBlock = 8;     // vectors per block of the register kernels (o
 constexpr int kRegMaxLen = 512;  // longest vector the register kernels hold
 constexpr int kSmallMax = 128;   // rows and row length of the one-workgroup register kernel
 constexpr size_t kWideLdsBytes = (size_t)kRegBlock * 2 * kRegMaxLen * sizeof(double2);  // one block in LDS
-constexpr int64_t kSplitWorkgroups = 256;  // register rounds split over two streams above this size
+constexpr int64_t kSplitWorkgroups = 256;  // register rounds split over streams above this size
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
@@ -448,44 +452,54 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
       return fail(MPS_ERR_STATE, "internal: Jacobi rotation counters not laid out [sweep][item]");
   JacobiPlanHost jp;
   plan_jacobi(all, jp);
-  // Register items in two groups on two streams.  One round of a large
+  // Register items in groups on their own streams.  One round of a large
   // batch launches more waves than the chip holds at once (two per SIMD at
   // this kernel's register use), so a launch runs as a full generation of
-  // waves plus a sparse second one; with the items dealt (largest first,
-  // alternately) into two groups whose rounds are queued on two streams,
-  // the waves of one group's round fill the slots the other's leaves idle.
-  // Every item still sees the same rounds in the same order as on one
-  // stream.
-  int reg_a = (int)jp.reg.size();
-  int pairs_a = jp.reg_pairs, pairs_b = 0, rounds_a = jp.reg_rounds, rounds_b = 0;
-  int maxm_a = jp.reg_max_m, maxm_b = 0;
+  // waves plus a sparse second one; with the items dealt (largest first, to
+  // the group with the least work so far) into groups whose rounds are
+  // queued on separate streams, the waves of one group's round fill the
+  // slots the others leave idle.  Every item still sees the same rounds in
+  // the same order as on one stream.
+  struct RegGroup {
+    int off = 0, count = 0, pairs = 0, rounds = 0, max_m = 0;
+    int64_t work = 0;
+  };
+  std::vector<RegGroup> groups(1);
+  groups[0].count = (int)jp.reg.size();
+  groups[0].pairs = jp.reg_pairs;
+  groups[0].rounds = jp.reg_rounds;
+  groups[0].max_m = jp.reg_max_m;
   {
     int64_t wgs = 0;
     for (const JacItem& it : jp.reg) wgs += it.nb / 2;
-    if (h->jacobi_split && jp.reg.size() >= 4 && wgs > kSplitWorkgroups) {
+    const int ng = std::min<int>(h->jacobi_groups, (int)jp.reg.size() / 2);
+    if (ng >= 2 && wgs > kSplitWorkgroups) {
       std::vector<JacItem> srt = jp.reg;
       std::stable_sort(srt.begin(), srt.end(), [](const JacItem& a, const JacItem& b) {
         return (int64_t)a.n * a.m > (int64_t)b.n * b.m;
       });
-      std::vector<JacItem> ga, gb;
-      for (size_t i = 0; i < srt.size(); ++i) (i & 1 ? gb : ga).push_back(srt[i]);
-      reg_a = (int)ga.size();
-      pairs_a = pairs_b = rounds_a = rounds_b = maxm_a = maxm_b = 0;
-      for (const JacItem& it : ga) {
-        pairs_a = std::max(pairs_a, it.nb / 2);
-        rounds_a = std::max(rounds_a, it.nb - 1);
-        maxm_a = std::max(maxm_a, it.m);
+      groups.assign(ng, RegGroup{});
+      std::vector<std::vector<JacItem>> members(ng);
+      for (const JacItem& it : srt) {
+        int g = 0;
+        for (int k = 1; k < ng; ++k)
+          if (groups[k].work < groups[g].work) g = k;
+        RegGroup& G = groups[g];
+        G.work += (int64_t)it.n * it.n * it.m;
+        G.pairs = std::max(G.pairs, it.nb / 2);
+        G.rounds = std::max(G.rounds, it.nb - 1);
+        G.max_m = std::max(G.max_m, it.m);
+        members[g].push_back(it);
       }
-      for (const JacItem& it : gb) {
-        pairs_b = std::max(pairs_b, it.nb / 2);
-        rounds_b = std::max(rounds_b, it.nb - 1);
-        maxm_b = std::max(maxm_b, it.m);
+      jp.reg.clear();
+      for (int g = 0; g < ng; ++g) {
+        groups[g].off = (int)jp.reg.size();
+        groups[g].count = (int)members[g].size();
+        jp.reg.insert(jp.reg.end(), members[g].begin(), members[g].end());
       }
-      jp.reg = ga;
-      jp.reg.insert(jp.reg.end(), gb.begin(), gb.end());
     }
   }
-  const int reg_b = (int)jp.reg.size() - reg_a;
+  const int n_groups = (int)groups.size();
   const size_t bytes =
       (jp.small.size() + jp.single.size() + jp.reg.size() + jp.block.size() + jp.wide.size()) *
       sizeof(JacItem);
@@ -537,21 +551,24 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   for (const JacItem& b : jp.wide) is_multi[b.rot - all[0].rot] = 1;
   const int nmulti = nmulti_items;
   const bool timed = h->timing && nmulti > 0;
-  if (reg_b > 0) {
-    if ((st = ensure_jside(h)) != MPS_OK) return st;
+  if (n_groups > 1) {
+    if ((st = ensure_jside(h, n_groups)) != MPS_OK) return st;
     HIP_TRY(h, hipEventRecord(h->ev_jfork, h->stream));
-    HIP_TRY(h, hipStreamWaitEvent(h->jside, h->ev_jfork, 0));
+    for (int g = 1; g < n_groups; ++g) HIP_TRY(h, hipStreamWaitEvent(h->jside[g - 1], h->ev_jfork, 0));
   }
-  // the handle's stream waits for the second group after every sweep (also
+  // the handle's stream waits for the other groups after every sweep (also
   // on an early return)
-  struct JoinB {
+  struct JoinGroups {
     mps_state* h;
+    int n;
     bool on;
-    ~JoinB() {
-      if (on && hipEventRecord(h->ev_jjoin, h->jside) == hipSuccess)
-        (void)hipStreamWaitEvent(h->stream, h->ev_jjoin, 0);
+    ~JoinGroups() {
+      if (!on) return;
+      for (int g = 1; g < n; ++g)
+        if (hipEventRecord(h->ev_jjoin[g - 1], h->jside[g - 1]) == hipSuccess)
+          (void)hipStreamWaitEvent(h->stream, h->ev_jjoin[g - 1], 0);
     }
-  } join_b{h, false};
+  } join_groups{h, n_groups, false};
   if (timed) {
     for (hipEvent_t& ev : h->ev_jac)
       if (!ev) HIP_TRY(h, hipEventCreate(&ev));
@@ -564,11 +581,12 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
     for (int sw = 0; sw < h->max_sweeps && done < nmulti; ++sw) {
       h->tm.jacobi_batch_sweeps += 1;
       for (int r = 0; r < rounds; ++r) {
-        if (reg_a > 0 && r < rounds_a)
-          HIP_TRY(h, launch_jacobi_reg(d_reg, reg_a, pairs_a, r, sw, kEpsScale, maxm_a, h->stream));
-        if (reg_b > 0 && r < rounds_b) {
-          join_b.on = true;
-          HIP_TRY(h, launch_jacobi_reg(d_reg + reg_a, reg_b, pairs_b, r, sw, kEpsScale, maxm_b, h->jside));
+        for (int g = 0; g < n_groups; ++g) {
+          const RegGroup& G = groups[g];
+          if (G.count == 0 || r >= G.rounds) continue;
+          join_groups.on = join_groups.on || g > 0;
+          HIP_TRY(h, launch_jacobi_reg(d_reg + G.off, G.count, G.pairs, r, sw, kEpsScale, G.max_m,
+                                       g == 0 ? h->stream : h->jside[g - 1]));
         }
         if (!jp.block.empty() && r < jp.block_rounds)
           HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
@@ -577,11 +595,11 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
           HIP_TRY(h, launch_jacobi_wide(d_wide, (int)jp.wide.size(), jp.wide_pairs, r, sw, kEpsScale,
                                         h->stream));
       }
-      if (reg_b > 0) {
-        HIP_TRY(h, hipEventRecord(h->ev_jjoin, h->jside));
-        HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_jjoin, 0));
-        join_b.on = false;
+      for (int g = 1; g < n_groups; ++g) {
+        HIP_TRY(h, hipEventRecord(h->ev_jjoin[g - 1], h->jside[g - 1]));
+        HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_jjoin[g - 1], 0));
       }
+      join_groups.on = false;
       if (sw >= 3 || sw == h->max_sweeps - 1) {
         HIP_TRY(h, hipMemcpyAsync(rot.data(), all[0].rot + (size_t)sw * count, sizeof(int) * count,
                                   hipMemcpyDeviceToHost, h->stream));
@@ -1760,7 +1778,8 @@ mps_status mps_destroy(mps_handle h) {
   if (!h) return MPS_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->side) (void)hipStreamSynchronize(h->side);
-  if (h->jside) (void)hipStreamSynchronize(h->jside);
+  for (hipStream_t js : h->jside)
+    if (js) (void)hipStreamSynchronize(js);
   drop_graph(h->ex);
   for (auto& a : h->allocs) (void)hipFree(a.first);
   for (hipEvent_t e : h->ev_env) (void)hipEventDestroy(e);
@@ -1769,9 +1788,11 @@ mps_status mps_destroy(mps_handle h) {
   for (hipEvent_t e : h->ev_jac)
     if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
-  if (h->jside) (void)hipStreamDestroy(h->jside);
+  for (hipStream_t js : h->jside)
+    if (js) (void)hipStreamDestroy(js);
+  for (hipEvent_t ev : h->ev_jjoin)
+    if (ev) (void)hipEventDestroy(ev);
   if (h->ev_jfork) (void)hipEventDestroy(h->ev_jfork);
-  if (h->ev_jjoin) (void)hipEventDestroy(h->ev_jjoin);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -2264,10 +2285,12 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
   return MPS_OK;
 }
 
-mps_status mps_set_jacobi_split(mps_handle h, int32_t enabled) {
+mps_status mps_set_jacobi_groups(mps_handle h, int32_t groups) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;
-  h->jacobi_split = enabled != 0;
+  if (groups < 1 || groups > kMaxJacobiGroups)
+    return fail(MPS_ERR_ARG, "jacobi groups must be 1.." + std::to_string(kMaxJacobiGroups));
+  h->jacobi_groups = groups;
   return MPS_OK;
 }
 
