@@ -144,7 +144,7 @@ mps_status mps_set_fused_gates(mps_handle h, int32_t enabled);
 
 /* Number of groups (1..3, default 2) into which the batched gate SVDs of
  * one brickwork layer are split, each group's Algorithm 1 rounds (register
- * kernels) queued on a stream of its own so that the rounds of one group
+ * and wide-row kernels) queued on a stream of its own so that the rounds of one group
  * fill the compute units the others leave idle.  Used only when a round
  * would launch more than 256 workgroups.  Each matrix sees the same
  * rotation rounds for every group count; 1 turns the split off (for

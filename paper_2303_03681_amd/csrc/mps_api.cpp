@@ -385,7 +385,7 @@ constexpr int kRegBlock = 8;     // vectors per block of the register kernels (o
 constexpr int kRegMaxLen = 512;  // longest vector the register kernels hold
 constexpr int kSmallMax = 128;   // rows and row length of the one-workgroup register kernel
 constexpr size_t kWideLdsBytes = (size_t)kRegBlock * 2 * kRegMaxLen * sizeof(double2);  // one block in LDS
-constexpr int64_t kSplitWorkgroups = 256;  // register rounds split over streams above this size
+constexpr int64_t kSplitWorkgroups = 256;  // multi-launch rounds split over streams above this size
 
 void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
   const size_t budget = g_lds_budget;
@@ -444,6 +444,56 @@ void plan_jacobi(const std::vector<JacItem>& all, JacobiPlanHost& jp) {
 // on device).  Item i must use rot = all[0].rot + i with rot_stride =
 // all.size(), zeroed for max_sweeps sweeps.  On return (after a stream sync)
 // `sweeps_out[i]` holds the sweeps used, or -1 if the sweep limit was hit.
+// Items of one multi-launch kind in groups whose rounds are queued on
+// separate streams.  One round of a large batch launches more waves than the
+// chip holds at once (two per SIMD at the register kernels' register use),
+// so a launch runs as a full generation of waves plus a sparse second one;
+// with the items dealt (largest first, to the group with the least work so
+// far) into groups on separate streams, the waves of one group's round fill
+// the slots the others leave idle.  Every item still sees the same rounds in
+// the same order as on one stream.  `items` is reordered group by group.
+struct ItemGroup {
+  int off = 0, count = 0, pairs = 0, rounds = 0, max_m = 0;
+  int64_t work = 0;
+};
+
+std::vector<ItemGroup> deal_groups(std::vector<JacItem>& items, int want, int pairs, int rounds,
+                                   int max_m) {
+  std::vector<ItemGroup> groups(1);
+  groups[0].count = (int)items.size();
+  groups[0].pairs = pairs;
+  groups[0].rounds = rounds;
+  groups[0].max_m = max_m;
+  int64_t wgs = 0;
+  for (const JacItem& it : items) wgs += it.nb / 2;
+  const int ng = std::min<int>(want, (int)items.size() / 2);
+  if (ng < 2 || wgs <= kSplitWorkgroups) return groups;
+  std::vector<JacItem> srt = items;
+  std::stable_sort(srt.begin(), srt.end(), [](const JacItem& a, const JacItem& b) {
+    return (int64_t)a.n * a.m > (int64_t)b.n * b.m;
+  });
+  groups.assign(ng, ItemGroup{});
+  std::vector<std::vector<JacItem>> members(ng);
+  for (const JacItem& it : srt) {
+    int g = 0;
+    for (int k = 1; k < ng; ++k)
+      if (groups[k].work < groups[g].work) g = k;
+    ItemGroup& G = groups[g];
+    G.work += (int64_t)it.n * it.n * it.m;
+    G.pairs = std::max(G.pairs, it.nb / 2);
+    G.rounds = std::max(G.rounds, it.nb - 1);
+    G.max_m = std::max(G.max_m, it.m);
+    members[g].push_back(it);
+  }
+  items.clear();
+  for (int g = 0; g < ng; ++g) {
+    groups[g].off = (int)items.size();
+    groups[g].count = (int)members[g].size();
+    items.insert(items.end(), members[g].begin(), members[g].end());
+  }
+  return groups;
+}
+
 mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc_off,
                       std::vector<int>& sweeps_out) {
   const int count = (int)all.size();
@@ -452,54 +502,13 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
       return fail(MPS_ERR_STATE, "internal: Jacobi rotation counters not laid out [sweep][item]");
   JacobiPlanHost jp;
   plan_jacobi(all, jp);
-  // Register items in groups on their own streams.  One round of a large
-  // batch launches more waves than the chip holds at once (two per SIMD at
-  // this kernel's register use), so a launch runs as a full generation of
-  // waves plus a sparse second one; with the items dealt (largest first, to
-  // the group with the least work so far) into groups whose rounds are
-  // queued on separate streams, the waves of one group's round fill the
-  // slots the others leave idle.  Every item still sees the same rounds in
-  // the same order as on one stream.
-  struct RegGroup {
-    int off = 0, count = 0, pairs = 0, rounds = 0, max_m = 0;
-    int64_t work = 0;
-  };
-  std::vector<RegGroup> groups(1);
-  groups[0].count = (int)jp.reg.size();
-  groups[0].pairs = jp.reg_pairs;
-  groups[0].rounds = jp.reg_rounds;
-  groups[0].max_m = jp.reg_max_m;
-  {
-    int64_t wgs = 0;
-    for (const JacItem& it : jp.reg) wgs += it.nb / 2;
-    const int ng = std::min<int>(h->jacobi_groups, (int)jp.reg.size() / 2);
-    if (ng >= 2 && wgs > kSplitWorkgroups) {
-      std::vector<JacItem> srt = jp.reg;
-      std::stable_sort(srt.begin(), srt.end(), [](const JacItem& a, const JacItem& b) {
-        return (int64_t)a.n * a.m > (int64_t)b.n * b.m;
-      });
-      groups.assign(ng, RegGroup{});
-      std::vector<std::vector<JacItem>> members(ng);
-      for (const JacItem& it : srt) {
-        int g = 0;
-        for (int k = 1; k < ng; ++k)
-          if (groups[k].work < groups[g].work) g = k;
-        RegGroup& G = groups[g];
-        G.work += (int64_t)it.n * it.n * it.m;
-        G.pairs = std::max(G.pairs, it.nb / 2);
-        G.rounds = std::max(G.rounds, it.nb - 1);
-        G.max_m = std::max(G.max_m, it.m);
-        members[g].push_back(it);
-      }
-      jp.reg.clear();
-      for (int g = 0; g < ng; ++g) {
-        groups[g].off = (int)jp.reg.size();
-        groups[g].count = (int)members[g].size();
-        jp.reg.insert(jp.reg.end(), members[g].begin(), members[g].end());
-      }
-    }
-  }
-  const int n_groups = (int)groups.size();
+  // Multi-launch items in groups on their own streams (register and wide
+  // rounds alike; group g of either kind runs on stream g).
+  std::vector<ItemGroup> groups = deal_groups(jp.reg, h->jacobi_groups, jp.reg_pairs, jp.reg_rounds,
+                                              jp.reg_max_m);
+  std::vector<ItemGroup> wgroups = deal_groups(jp.wide, h->jacobi_groups, jp.wide_pairs,
+                                               jp.wide_rounds, 0);
+  const int n_groups = (int)std::max(groups.size(), wgroups.size());
   const size_t bytes =
       (jp.small.size() + jp.single.size() + jp.reg.size() + jp.block.size() + jp.wide.size()) *
       sizeof(JacItem);
@@ -581,8 +590,8 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
     for (int sw = 0; sw < h->max_sweeps && done < nmulti; ++sw) {
       h->tm.jacobi_batch_sweeps += 1;
       for (int r = 0; r < rounds; ++r) {
-        for (int g = 0; g < n_groups; ++g) {
-          const RegGroup& G = groups[g];
+        for (int g = 0; g < (int)groups.size(); ++g) {
+          const ItemGroup& G = groups[g];
           if (G.count == 0 || r >= G.rounds) continue;
           join_groups.on = join_groups.on || g > 0;
           HIP_TRY(h, launch_jacobi_reg(d_reg + G.off, G.count, G.pairs, r, sw, kEpsScale, G.max_m,
@@ -591,9 +600,13 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
         if (!jp.block.empty() && r < jp.block_rounds)
           HIP_TRY(h, launch_jacobi_block(d_block, (int)jp.block.size(), jp.block_pairs, r, sw,
                                          kEpsScale, jp.block_lds, h->stream));
-        if (!jp.wide.empty() && r < jp.wide_rounds)
-          HIP_TRY(h, launch_jacobi_wide(d_wide, (int)jp.wide.size(), jp.wide_pairs, r, sw, kEpsScale,
-                                        h->stream));
+        for (int g = 0; g < (int)wgroups.size(); ++g) {
+          const ItemGroup& G = wgroups[g];
+          if (G.count == 0 || r >= G.rounds) continue;
+          join_groups.on = join_groups.on || g > 0;
+          HIP_TRY(h, launch_jacobi_wide(d_wide + G.off, G.count, G.pairs, r, sw, kEpsScale,
+                                        g == 0 ? h->stream : h->jside[g - 1]));
+        }
       }
       for (int g = 1; g < n_groups; ++g) {
         HIP_TRY(h, hipEventRecord(h->ev_jjoin[g - 1], h->jside[g - 1]));
