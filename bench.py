@@ -396,7 +396,7 @@ def main():
         "peak": 78.6,
         "unit": "TFLOP/s",
         "frac": jac_tflops / 78.6,
-        "kernel": "jacobi_reg_full/cross (Algorithm 1 rounds of the batched gate SVDs and canonicalisation)",
+        "kernel": "jacobi_reg_intra/cross (Algorithm 1 rounds of the batched gate SVDs and canonicalisation)",
         "flops_per_step": tm["jacobi_flops"] / K,
         "device_ms_per_step": tm["jacobi_ms"] / K,
         "note": "FP64 vector peak; 32m FLOPs per rotated pair, 8m per pair visited without rotation",

@@ -398,32 +398,19 @@ __device__ __forceinline__ void reg_epilogue(const RegCtx& c, int rot, int* s_ro
   }
 }
 
-// Outer round 0: all pairs of the 16 vectors of blocks bp and bq by the
-// circle method.  Wave i holds positions i (x) and 15 - i (y); positions
-// 1..15 advance by one each inner round through 2 x 8 LDS slots.
-template <int E>
-__global__ __launch_bounds__(JW * 64) void jacobi_reg_full_kernel(const JacItem* items, int max_pairs,
-                                                                  int round, int sweep,
-                                                                  double eps_scale) {
-  extern __shared__ double2 slots[];  // 2 * JW slots of 64 * E elements
-  __shared__ int s_rot;
-  __shared__ int g_top[JW], g_bot[JW];
-  RegCtx c;
-  if (!reg_prologue(items, max_pairs, round, sweep, eps_scale, c)) return;
-  const int m = c.it.m, n = c.it.n;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_rot = 0;
-  RegVec<E> x, y;
-  int gx = c.bp * JW + wv, gy = c.bq * JW + (JW - 1 - wv);
-  gx = gx < n ? gx : -1;
-  gy = gy < n ? gy : -1;
-  rv_load<E>(x, c.it.w + (size_t)max(gx, 0) * m, gx >= 0, m, lane);
-  rv_load<E>(y, c.it.w + (size_t)max(gy, 0) * m, gy >= 0, m, lane);
+// Circle method over the 2W rows that W waves hold (wave w: positions w and
+// 2W - 1 - w): every pair of them is visited once in 2W - 1 steps; after
+// each step positions 1..2W-1 advance by one through 2 x W LDS slots
+// (position 0 fixed).  gx, gy follow the rows (global indices, -1 padding).
+template <int E, int W>
+__device__ __forceinline__ int circle_pairs(RegVec<E>& x, int& gx, RegVec<E>& y, int& gy, double2* slots,
+                                            int* g_top, int* g_bot, double eps, double floor, int lane,
+                                            int wv) {
   double2* top = slots;
-  double2* bot = slots + (size_t)JW * 64 * E;
+  double2* bot = slots + (size_t)W * 64 * E;
   int rot = 0;
-  for (int t = 0; t < 2 * JW - 1; ++t) {
-    rot += jacobi_pair_ordered<E>(x, gx, y, gy, c.eps, c.floor);
+  for (int t = 0; t < 2 * W - 1; ++t) {
+    rot += jacobi_pair_ordered<E>(x, gx, y, gy, eps, floor);
     rv_to_lds<E>(x, top + (size_t)wv * 64 * E, lane);
     rv_to_lds<E>(y, bot + (size_t)wv * 64 * E, lane);
     if (lane == 0) {
@@ -431,14 +418,52 @@ __global__ __launch_bounds__(JW * 64) void jacobi_reg_full_kernel(const JacItem*
       g_bot[wv] = gy;
     }
     __syncthreads();
-    // new pos j+1 <- old pos j for j = 1..14, new pos 1 <- old pos 15, pos 0 fixed
+    // new pos j+1 <- old pos j for j = 1..2W-2, new pos 1 <- old pos 2W-1, pos 0 fixed
     if (wv >= 2) { rv_from_lds<E>(x, top + (size_t)(wv - 1) * 64 * E, lane); gx = g_top[wv - 1]; }
     if (wv == 1) { rv_from_lds<E>(x, bot, lane); gx = g_bot[0]; }
-    if (wv <= JW - 2) { rv_from_lds<E>(y, bot + (size_t)(wv + 1) * 64 * E, lane); gy = g_bot[wv + 1]; }
-    if (wv == JW - 1) { rv_from_lds<E>(y, top + (size_t)(JW - 1) * 64 * E, lane); gy = g_top[JW - 1]; }
+    if (wv <= W - 2) { rv_from_lds<E>(y, bot + (size_t)(wv + 1) * 64 * E, lane); gy = g_bot[wv + 1]; }
+    if (wv == W - 1) { rv_from_lds<E>(y, top + (size_t)(W - 1) * 64 * E, lane); gy = g_top[W - 1]; }
     __syncthreads();
   }
-  reg_epilogue<E>(c, rot, &s_rot, x, gx, y, gy, sweep);
+  return rot;
+}
+
+// The 28 pairs inside each block of 8 rows, one 4-wave workgroup per block
+// (rows b*8 + w and b*8 + 7 - w on wave w), for every block of every item.
+// Run before outer round 0 of a sweep, whose cross pairs the cross kernel
+// then takes: over the sweep every pair of the matrix is visited once.
+constexpr int IW = JW / 2;
+
+template <int E>
+__global__ __launch_bounds__(IW * 64) void jacobi_reg_intra_kernel(const JacItem* items, int max_blocks,
+                                                                   int sweep, double eps_scale) {
+  extern __shared__ double2 slots[];  // 2 * IW slots of 64 * E elements
+  __shared__ int s_rot;
+  __shared__ int g_top[IW], g_bot[IW];
+  const int item = blockIdx.x / max_blocks;
+  const int b = blockIdx.x - item * max_blocks;
+  const JacItem it = items[item];
+  if (b >= it.nb) return;
+  if (sweep > 0 && it.rot[(sweep - 1) * it.rot_stride] == 0) return;  // converged
+  const int m = it.m, n = it.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_rot = 0;
+  const double eps = eps_scale * (double)m;
+  const double floor = eps * eps * (*it.fro2);
+  RegVec<E> x, y;
+  int gx = b * JW + wv, gy = b * JW + (JW - 1 - wv);
+  gx = gx < n ? gx : -1;
+  gy = gy < n ? gy : -1;
+  rv_load<E>(x, it.w + (size_t)max(gx, 0) * m, gx >= 0, m, lane);
+  rv_load<E>(y, it.w + (size_t)max(gy, 0) * m, gy >= 0, m, lane);
+  const int rot = circle_pairs<E, IW>(x, gx, y, gy, slots, g_top, g_bot, eps, floor, lane, wv);
+  if (lane == 0 && rot) atomicAdd(&s_rot, rot);
+  __syncthreads();
+  if (s_rot > 0) {
+    if (gx >= 0) rv_store<E>(x, it.w + (size_t)gx * m, m, lane);
+    if (gy >= 0) rv_store<E>(y, it.w + (size_t)gy * m, m, lane);
+    if (threadIdx.x == 0) atomicAdd(&it.rot[sweep * it.rot_stride], s_rot);
+  }
 }
 
 // Two disjoint pairs (x0, y0), (x1, y1) with their squared norms tracked:
@@ -578,13 +603,14 @@ __global__ __launch_bounds__(CW * 64, 2) void jacobi_reg_cross_kernel(const JacI
 template <int E>
 hipError_t launch_reg_e(const JacItem* items_dev, int items, int max_pairs, int round, int sweep,
                         double eps_scale, hipStream_t s) {
-  const dim3 grid(items * max_pairs), block(JW * 64);
-  if (round == 0)
-    hipLaunchKernelGGL(jacobi_reg_full_kernel<E>, grid, block, 2 * JW * 64 * E * sizeof(double2), s,
-                       items_dev, max_pairs, round, sweep, eps_scale);
-  else
-    hipLaunchKernelGGL(jacobi_reg_cross_kernel<E>, grid, dim3(CW * 64), CW * 2 * 64 * E * sizeof(double2),
-                       s, items_dev, max_pairs, round, sweep, eps_scale);
+  if (round == 0) {  // in-block pairs of every block first (nb = 2 * pairs blocks per item)
+    hipLaunchKernelGGL(jacobi_reg_intra_kernel<E>, dim3(items * 2 * max_pairs), dim3(IW * 64),
+                       2 * IW * 64 * E * sizeof(double2), s, items_dev, 2 * max_pairs, sweep, eps_scale);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(jacobi_reg_cross_kernel<E>, dim3(items * max_pairs), dim3(CW * 64),
+                     CW * 2 * 64 * E * sizeof(double2), s, items_dev, max_pairs, round, sweep, eps_scale);
   return hipGetLastError();
 }
 
@@ -753,8 +779,8 @@ __global__ __launch_bounds__(512) void jacobi_single_kernel(const JacItem* items
 
 hipError_t configure_jacobi_lds(size_t bytes) {
   const void* fns[] = {(const void*)jacobi_block_kernel, (const void*)jacobi_single_kernel,
-                       (const void*)jacobi_reg_full_kernel<1>, (const void*)jacobi_reg_full_kernel<2>,
-                       (const void*)jacobi_reg_full_kernel<4>, (const void*)jacobi_reg_full_kernel<8>,
+                       (const void*)jacobi_reg_intra_kernel<1>, (const void*)jacobi_reg_intra_kernel<2>,
+                       (const void*)jacobi_reg_intra_kernel<4>, (const void*)jacobi_reg_intra_kernel<8>,
                        (const void*)jacobi_reg_cross_kernel<1>, (const void*)jacobi_reg_cross_kernel<2>,
                        (const void*)jacobi_reg_cross_kernel<4>, (const void*)jacobi_reg_cross_kernel<8>};
   for (const void* f : fns) {
