@@ -269,15 +269,14 @@ __global__ __launch_bounds__(512) void jacobi_block_kernel(const JacItem* items,
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident block Jacobi.  A workgroup of JW = 8 waves owns one block
-// pair (2 x 8 vectors); each lane keeps E elements (e = lane + 64 k) of the
-// vectors its wave holds, so dot products and rotations never touch LDS.
-// Outer round 0 of a sweep pairs every block with exactly one other block and
-// sweeps all 120 pairs of the 16 vectors (circle method, both vectors of a
-// wave move each inner round); every later outer round only needs the 64
-// cross pairs: each wave keeps its resident vector from block p and the
-// travellers from block q move one wave along per inner round.  Over one
-// outer sweep every pair of the matrix is visited once.
+// Register-resident block Jacobi on blocks of JW = 8 vectors; each lane keeps
+// E elements (e = lane + 64 k) of the vectors its wave holds, so dot products
+// and rotations never touch LDS.  A sweep is one launch for the 28 pairs
+// inside every block (circle method, both vectors of a wave move each inner
+// round), then one launch per outer round of the block round-robin, each
+// pairing every block with exactly one other and taking the 64 cross pairs
+// of the two (resident vectors stay, travellers move one wave along per
+// inner round).  Over one sweep every pair of the matrix is visited once.
 constexpr int JW = 8;
 
 template <int E>
@@ -536,7 +535,7 @@ __device__ __forceinline__ double rv_norm2(const RegVec<E>& r) {
   return wave_sum(s);
 }
 
-// Outer rounds >= 1: the 64 cross pairs of blocks bp and bq on CW = 4 waves.
+// Every outer round: the 64 cross pairs of blocks bp and bq on CW = 4 waves.
 // Wave w keeps resident rows bp*8 + 2w, 2w + 1 and holds two travellers from
 // block bq, which move one wave along per step through LDS (4 steps) with
 // their squared norms; each step is two sub-steps of two disjoint pairs.
