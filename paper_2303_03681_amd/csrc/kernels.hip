@@ -400,29 +400,51 @@ __device__ __forceinline__ void reg_epilogue(const RegCtx& c, int rot, int* s_ro
 // Circle method over the 2W rows that W waves hold (wave w: positions w and
 // 2W - 1 - w): every pair of them is visited once in 2W - 1 steps; after
 // each step positions 1..2W-1 advance by one through 2 x W LDS slots
-// (position 0 fixed).  gx, gy follow the rows (global indices, -1 padding).
-template <int E, int W>
+// (position 0 fixed), in C chunks of E / C elements per lane so that the
+// slots take 2 W 64 (E / C) elements.  gx, gy follow the rows (global
+// indices, -1 padding).
+template <int E, int W, int C>
 __device__ __forceinline__ int circle_pairs(RegVec<E>& x, int& gx, RegVec<E>& y, int& gy, double2* slots,
                                             int* g_top, int* g_bot, double eps, double floor, int lane,
                                             int wv) {
+  static_assert(E % C == 0, "chunks must divide the elements per lane");
+  constexpr int EC = E / C;
   double2* top = slots;
-  double2* bot = slots + (size_t)W * 64 * E;
+  double2* bot = slots + (size_t)W * 64 * EC;
   int rot = 0;
   for (int t = 0; t < 2 * W - 1; ++t) {
     rot += jacobi_pair_ordered<E>(x, gx, y, gy, eps, floor);
-    rv_to_lds<E>(x, top + (size_t)wv * 64 * E, lane);
-    rv_to_lds<E>(y, bot + (size_t)wv * 64 * E, lane);
-    if (lane == 0) {
-      g_top[wv] = gx;
-      g_bot[wv] = gy;
+    int nx = gx, ny = gy;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+      for (int k = 0; k < EC; ++k) {
+        top[((size_t)wv * EC + k) * 64 + lane] = x.v[c * EC + k];
+        bot[((size_t)wv * EC + k) * 64 + lane] = y.v[c * EC + k];
+      }
+      if (c == 0 && lane == 0) {
+        g_top[wv] = gx;
+        g_bot[wv] = gy;
+      }
+      __syncthreads();
+      // new pos j+1 <- old pos j for j = 1..2W-2, new pos 1 <- old pos 2W-1, pos 0 fixed
+      const double2* sx = wv >= 2 ? top + (size_t)(wv - 1) * EC * 64 : (wv == 1 ? bot : nullptr);
+      const double2* sy = wv <= W - 2 ? bot + (size_t)(wv + 1) * EC * 64 : top + (size_t)(W - 1) * EC * 64;
+      if (sx) {
+#pragma unroll
+        for (int k = 0; k < EC; ++k) x.v[c * EC + k] = sx[(size_t)k * 64 + lane];
+      }
+#pragma unroll
+      for (int k = 0; k < EC; ++k) y.v[c * EC + k] = sy[(size_t)k * 64 + lane];
+      if (c == 0) {
+        if (wv >= 2) nx = g_top[wv - 1];
+        if (wv == 1) nx = g_bot[0];
+        ny = wv <= W - 2 ? g_bot[wv + 1] : g_top[W - 1];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // new pos j+1 <- old pos j for j = 1..2W-2, new pos 1 <- old pos 2W-1, pos 0 fixed
-    if (wv >= 2) { rv_from_lds<E>(x, top + (size_t)(wv - 1) * 64 * E, lane); gx = g_top[wv - 1]; }
-    if (wv == 1) { rv_from_lds<E>(x, bot, lane); gx = g_bot[0]; }
-    if (wv <= W - 2) { rv_from_lds<E>(y, bot + (size_t)(wv + 1) * 64 * E, lane); gy = g_bot[wv + 1]; }
-    if (wv == W - 1) { rv_from_lds<E>(y, top + (size_t)(W - 1) * 64 * E, lane); gy = g_top[W - 1]; }
-    __syncthreads();
+    gx = nx;
+    gy = ny;
   }
   return rot;
 }
@@ -430,13 +452,17 @@ __device__ __forceinline__ int circle_pairs(RegVec<E>& x, int& gx, RegVec<E>& y,
 // The 28 pairs inside each block of 8 rows, one 4-wave workgroup per block
 // (rows b*8 + w and b*8 + 7 - w on wave w), for every block of every item.
 // Run before outer round 0 of a sweep, whose cross pairs the cross kernel
-// then takes: over the sweep every pair of the matrix is visited once.
+// then takes: over the sweep every pair of the matrix is visited once.  The
+// rows move through LDS in two halves (32 KB at E = 8), so that LDS allows
+// as many resident workgroups as the registers do.
 constexpr int IW = JW / 2;
+template <int E>
+constexpr int intra_chunks() { return E >= 2 ? 2 : 1; }
 
 template <int E>
 __global__ __launch_bounds__(IW * 64) void jacobi_reg_intra_kernel(const JacItem* items, int max_blocks,
                                                                    int sweep, double eps_scale) {
-  extern __shared__ double2 slots[];  // 2 * IW slots of 64 * E elements
+  extern __shared__ double2 slots[];  // 2 * IW slots of 64 * E / intra_chunks<E>() elements
   __shared__ int s_rot;
   __shared__ int g_top[IW], g_bot[IW];
   const int item = blockIdx.x / max_blocks;
@@ -455,7 +481,7 @@ __global__ __launch_bounds__(IW * 64) void jacobi_reg_intra_kernel(const JacItem
   gy = gy < n ? gy : -1;
   rv_load<E>(x, it.w + (size_t)max(gx, 0) * m, gx >= 0, m, lane);
   rv_load<E>(y, it.w + (size_t)max(gy, 0) * m, gy >= 0, m, lane);
-  const int rot = circle_pairs<E, IW>(x, gx, y, gy, slots, g_top, g_bot, eps, floor, lane, wv);
+  const int rot = circle_pairs<E, IW, intra_chunks<E>()>(x, gx, y, gy, slots, g_top, g_bot, eps, floor, lane, wv);
   if (lane == 0 && rot) atomicAdd(&s_rot, rot);
   __syncthreads();
   if (s_rot > 0) {
@@ -604,7 +630,8 @@ hipError_t launch_reg_e(const JacItem* items_dev, int items, int max_pairs, int 
                         double eps_scale, hipStream_t s) {
   if (round == 0) {  // in-block pairs of every block first (nb = 2 * pairs blocks per item)
     hipLaunchKernelGGL(jacobi_reg_intra_kernel<E>, dim3(items * 2 * max_pairs), dim3(IW * 64),
-                       2 * IW * 64 * E * sizeof(double2), s, items_dev, 2 * max_pairs, sweep, eps_scale);
+                       2 * IW * 64 * (E / intra_chunks<E>()) * sizeof(double2), s, items_dev, 2 * max_pairs,
+                       sweep, eps_scale);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
