@@ -7,16 +7,17 @@ hardware-efficient brickwork ansatz of 20 layers (Ry, Rz, CNOT ladders) with
 angles U(-pi, pi), bond dimension 256.
 
 One step = one whole energy evaluation on the device: reset to the
-Hartree-Fock product state, apply every gate (two-site contraction,
-Jacobi SVD, truncation), canonicalise, evaluate all 2^18 strings and sum
-the energy.  value = strings / (time per step).
+Hartree-Fock product state, apply every gate (two-site contraction, Jacobi
+SVD, truncation), then evaluate all 2^18 strings from the identity
+environments of both boundaries (divided by <psi|psi>; no canonicalisation
+sweep) and sum the energy.  value = strings / (time per step).
 
-The environment products run in the precision given by --prec (default
-c64: FP32 MFMA; gates, SVDs, canonical form, closing traces and the energy
-sum stay FP64); one extra step in c128 (FP64 MFMA) gives the reference
-energy and the complex128 rate.
+The headline steps run in complex128 (FP64 MFMA environments, FP64
+everywhere else; --prec changes it).  The FP32 (c64) and split-16-bit
+environment precisions are then timed over the same K steps, each with its
+own roofline and its energy difference from the headline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec c64|c128]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec c128|c64|...]
 """
 
 from __future__ import annotations
@@ -45,15 +46,15 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, n_strings_sample: int = 24, n_gates_sample: int = 2) -> dict:
-    """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload, extrapolated to one whole energy evaluation (strings/s)."""
+def _oracle_sample(w, n_strings_sample: int, n_gates_sample: int) -> dict:
+    """Times the oracle's pieces of one evaluation on a random canonical state
+    of the workload's shape: full-size two-qubit gates in the middle of the
+    chain, one canonicalisation, and per-string expectations."""
     from oracle import MpsOracle
     from workloads.circuits import gate_cnot
 
     n, D = w.n_qubits, w.spec.max_bond
     rng = np.random.default_rng(12345)
-    # a canonical D=256 state of the workload's shape (setup, untimed)
     o = MpsOracle(n, D, 1e-14, w.bits)
     dims = [min(D, 2 ** min(b, n - b)) for b in range(n + 1)]
     o.B = [(rng.normal(size=(2, dims[q], dims[q + 1]))
@@ -62,7 +63,6 @@ def cpu_baseline(w, n_strings_sample: int = 24, n_gates_sample: int = 2) -> dict
     t0 = time.perf_counter()
     o.canonicalize()
     t_canon = time.perf_counter() - t0
-    # full-size two-qubit gates in the middle of the chain
     t0 = time.perf_counter()
     for i in range(n_gates_sample):
         o.apply_2q(n // 2 - 1 + (i % 2), gate_cnot())
@@ -75,20 +75,40 @@ def cpu_baseline(w, n_strings_sample: int = 24, n_gates_sample: int = 2) -> dict
     t_str = (time.perf_counter() - t0) / n_strings_sample
     n2q = sum(1 for g in w.gates if g.q1 >= 0)
     t_eval = n2q * t_gate + t_canon + w.psum.n_terms * t_str
+    return {"value": w.psum.n_terms / t_eval, "t_str": t_str, "t_gate": t_gate, "t_canon": t_canon,
+            "n2q": n2q, "strings": n_strings_sample, "gates": n_gates_sample}
+
+
+def cpu_baseline(w, n_strings_sample: int = 24, n_gates_sample: int = 2) -> dict:
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload, extrapolated to one whole energy evaluation (strings/s): with
+    every core as BLAS threads, and again with one thread."""
+    from threadpoolctl import threadpool_limits
+
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    with threadpool_limits(limits=threads):
+        a = _oracle_sample(w, n_strings_sample, n_gates_sample)
+    with threadpool_limits(limits=1):
+        b = _oracle_sample(w, max(4, n_strings_sample // 3), 1)
+    D = w.spec.max_bond
+
+    def desc(r):
+        return (f"{r['strings']} of {w.psum.n_terms} strings, {r['gates']} of {r['n2q']} two-qubit gates "
+                f"at D={D} and one canonicalisation, timed on a random canonical D={D} state and "
+                f"extrapolated to one energy evaluation ({r['t_str'] * 1e3:.1f} ms/string, "
+                f"{r['t_gate']:.2f} s/gate, {r['t_canon']:.1f} s/canonicalise)")
+
     return {
-        "value": w.psum.n_terms / t_eval,
+        "value": a["value"],
         "unit": "Pauli-string expectations/s",
-        "cores": min(cores, threads),
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"{n_strings_sample} of {w.psum.n_terms} strings, {n_gates_sample} of {n2q} "
-                   f"two-qubit gates at D={D} and one canonicalisation, timed on a random "
-                   f"canonical D={D} state and extrapolated to one energy evaluation "
-                   f"({t_str * 1e3:.1f} ms/string, {t_gate:.2f} s/gate, {t_canon:.1f} s/canonicalise)"),
+        "sample": desc(a),
+        "one_thread": {"value": b["value"], "cores": 1, "sample": desc(b)},
     }
 
 
@@ -234,12 +254,36 @@ def autotune_summary(binding, enabled):
             "tuning_run_ms_chosen_vs_default": [chosen, default]}
 
 
+def env_roofline(tm, prec):
+    """The environment-update kernels (a10) against their MFMA peak: algorithmic
+    FLOPs of the launches over their HIP-event durations."""
+    rate = tm["env_flops"] / (tm["env_ms"] * 1e-3) / 1e12 if tm["env_ms"] > 0 else 0.0
+    peak = PEAK_TFLOPS["c128" if prec == "c128" else "c64"]
+    return {
+        "bound": "mfma",
+        "achieved": rate,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": rate / peak,
+        "traffic": ENV_TRAFFIC_BYTES.get(prec),
+        "traffic_unit": "bytes per launch (HBM, scaled PMC FETCH_SIZE + WRITE_SIZE)",
+        "kernel": "cgemm_kernel<EnvG1P/EnvG2P> (transfer-matrix update)" if prec in ("c128", "c64")
+        else "cgemm_split_kernel<EnvG1P/EnvG2P> (transfer-matrix update)",
+        "flops_per_launch": tm["env_flops"] / max(1, tm["env_launches"]),
+        "avg_launch_ms": tm["env_ms"] / max(1, tm["env_launches"]),
+        "launches": tm["env_launches"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="c64", choices=["c64", "c128", "split_bf16", "split_f16"])
+    ap.add_argument("--prec", default="c128", choices=["c64", "c128", "split_bf16", "split_f16"],
+                    help="precision of the headline steps (default c128: FP64 throughout)")
+    ap.add_argument("--other-precisions", default="c64,split_f16,split_bf16",
+                    help="precisions timed over the same K steps after the headline ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layers", type=int, default=None, help="override (smaller) layer count")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix sample")
@@ -290,7 +334,7 @@ def main():
     log(f"plan in {time.perf_counter() - t0:.1f} s: {st}")
     m = binding.Mps(w.n_qubits, w.spec.max_bond, w.spec.cutoff, bits=w.bits,
                     stream=stream.cuda_stream)
-    m.set_autotune(not args.no_autotune)  # tile tuning happens in the first (warmup) expectation
+    m.set_autotune(not args.no_autotune)  # tile tuning happens in the first expectation per precision
     m.set_jacobi_groups(args.jacobi_groups)
 
     def step(prec, verbose=False):
@@ -302,44 +346,56 @@ def main():
                 m.apply_gates(q0[a:a + per], q1[a:a + per], u[a:a + per])
                 log(f"  gates {a}..{min(len(q0), a + per)}: {time.perf_counter() - t1:.2f} s, "
                     f"max bond {int(m.bond_dims().max())}")
-            t1 = time.perf_counter()
-            m.canonicalize()
-            log(f"  canonicalize: {time.perf_counter() - t1:.2f} s")
         else:
             m.apply_gates(q0, q1, u)
         return m.expect(plan, prec)
+
+    def timed_steps(prec):
+        """K whole evaluations in `prec`, bracketed by device synchronisation."""
+        m.set_timing(True)
+        torch.cuda.synchronize()
+        times, energies = [], []
+        t_all = time.perf_counter()
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            energies.append(step(prec))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+            log(f"{prec} step {i}: {times[-1]:.3f} s, E = {energies[-1]:.12f}")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        return total, times, energies, m.timing()
 
     for i in range(args.warmup):
         t1 = time.perf_counter()
         e = step(args.prec, verbose=(i == 0))
         log(f"warmup {i}: {time.perf_counter() - t1:.2f} s, E = {e:.12f}")
-    m.set_timing(True)
-    torch.cuda.synchronize()
-    times, energies = [], []
-    t_all = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        energies.append(step(args.prec))
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        log(f"step {i}: {times[-1]:.3f} s, E = {energies[-1]:.12f}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_all
-    tm = m.timing()
+    total, times, energies, tm = timed_steps(args.prec)
     dims = m.bond_dims()
     disc = m.discarded_weight()
-    # complex128 reference step (same gates; environments in FP64); its tile
-    # classes are tuned first, untimed, on the final state (same bond dims)
-    t1 = time.perf_counter()
-    m.expect(plan, "c128")
-    log(f"c128 setup{'' if args.no_autotune else ' + tile tuning'}: {time.perf_counter() - t1:.2f} s")
-    m.set_timing(True)
-    ts = time.perf_counter()
-    e128 = step("c128")
-    torch.cuda.synchronize()
-    t128 = time.perf_counter() - ts
-    tm128 = m.timing()
-    log(f"c128 step: {t128:.3f} s, E = {e128:.12f}")
+    K = args.steps
+    lat = np.array(times) * 1e3
+
+    # the other precisions over the same K whole evaluations; each precision's
+    # tile classes are tuned first, untimed, on the final state (same bond dims)
+    others = [p for p in args.other_precisions.split(",") if p and p != args.prec]
+    per_prec = {}
+    e_head = float(np.mean(energies))
+    for pr in others:
+        t1 = time.perf_counter()
+        m.expect(plan, pr)
+        log(f"{pr} setup{'' if args.no_autotune else ' + tile tuning'}: {time.perf_counter() - t1:.2f} s")
+        tot_p, times_p, en_p, tm_p = timed_steps(pr)
+        lat_p = np.array(times_p) * 1e3
+        per_prec[pr] = {
+            "value": w.psum.n_terms / (tot_p / K), "ms_per_step": 1e3 * tot_p / K,
+            "latency_ms": {"p50": float(np.percentile(lat_p, 50)), "p99": float(np.percentile(lat_p, 99))},
+            "energy": float(np.mean(en_p)),
+            "abs_dE_vs_" + args.prec: abs(float(np.mean(en_p)) - e_head),
+            "phases_ms_per_step": {"gates": tm_p["gates_ms"] / K, "expect": tm_p["expect_ms"] / K,
+                                   "env_kernels": tm_p["env_ms"] / K, "close_kernels": tm_p["close_ms"] / K},
+            "roofline": env_roofline(tm_p, pr),
+        }
 
     # expectation phase alone on the final state, every precision
     precisions = {}
@@ -370,25 +426,10 @@ def main():
         log(f"expect {pr}: {d['expect_ms']:.1f} ms, env {d['env_tflops_algorithmic']:.1f} TFLOP/s, "
             f"|dE| {d['abs_dE_vs_c128']:.2e}")
 
-    K = args.steps
     ms_per_step = 1e3 * total / K
     value = w.psum.n_terms / (total / K)
-    env_tflops = tm["env_flops"] / (tm["env_ms"] * 1e-3) / 1e12 if tm["env_ms"] > 0 else 0.0
-    peak = PEAK_TFLOPS[args.prec]
-    launches_per_step = tm["env_launches"] / K
-    roofline = {
-        "bound": "mfma",
-        "achieved": env_tflops,
-        "peak": peak,
-        "unit": "TFLOP/s",
-        "frac": env_tflops / peak,
-        "traffic": ENV_TRAFFIC_BYTES.get(args.prec),
-        "traffic_unit": "bytes per launch (HBM, scaled PMC FETCH_SIZE + WRITE_SIZE)",
-        "kernel": "cgemm_kernel<EnvG1P/EnvG2P> (transfer-matrix update)",
-        "flops_per_launch": tm["env_flops"] / max(1, tm["env_launches"]),
-        "avg_launch_ms": tm["env_ms"] / max(1, tm["env_launches"]),
-        "launches_per_step": launches_per_step,
-    }
+    roofline = env_roofline(tm, args.prec)
+    roofline["launches_per_step"] = tm["env_launches"] / K
     jac_tflops = tm["jacobi_flops"] / (tm["jacobi_ms"] * 1e-3) / 1e12 if tm["jacobi_ms"] > 0 else 0.0
     roofline_jacobi = {
         "bound": "alu",
@@ -396,13 +437,11 @@ def main():
         "peak": 78.6,
         "unit": "TFLOP/s",
         "frac": jac_tflops / 78.6,
-        "kernel": "jacobi_reg_intra/cross (Algorithm 1 rounds of the batched gate SVDs and canonicalisation)",
+        "kernel": "jacobi_reg_intra/cross (Algorithm 1 rounds of the batched gate SVDs)",
         "flops_per_step": tm["jacobi_flops"] / K,
         "device_ms_per_step": tm["jacobi_ms"] / K,
         "note": "FP64 vector peak; 32m FLOPs per rotated pair, 8m per pair visited without rotation",
     }
-    env128 = tm128["env_flops"] / (tm128["env_ms"] * 1e-3) / 1e12 if tm128["env_ms"] > 0 else 0.0
-    lat = np.array(times) * 1e3
     out = {
         "metric": METRIC,
         "value": value,
@@ -414,8 +453,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("c64 environments (FP32 MFMA), FP64 gates/SVD/boundary environments/norm/closes/sum"
-                  if args.prec == "c64" else "c128 (FP64 MFMA) throughout"),
+        "dtype": ("c128 (FP64 MFMA) throughout" if args.prec == "c128" else
+                  f"{args.prec} environments, FP64 gates/SVD/boundary environments/norm/closes/sum"),
         "data": "synthetic (seeded random-integral JW Hamiltonian, random brickwork angles)",
         "config": {
             "workload": "50q brickwork-20 D=256, 2^18 sampled JW strings (one energy evaluation per step)",
@@ -424,20 +463,20 @@ def main():
             "n_strings": w.psum.n_terms, "two_qubit_gates": n2q, "prec": args.prec,
         },
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "energy": float(np.mean(energies)),
-        "energy_c128": e128,
-        "abs_dE_vs_c128": abs(float(np.mean(energies)) - e128),
-        "c128_path": {"value": w.psum.n_terms / t128, "ms_per_step": 1e3 * t128,
-                      "env_tflops": env128, "env_frac_fp64_peak": env128 / PEAK_TFLOPS["c128"]},
-        "phases_ms_per_step": {"gates": tm["gates_ms"] / K, "canonicalize": tm["canon_ms"] / K,
-                               "expect": tm["expect_ms"] / K, "env_kernels": tm["env_ms"] / K,
-                               "close_kernels": tm["close_ms"] / K},
-        "close": {"tflops_fp64": (tm["close_flops"] / (tm["close_ms"] * 1e-3) / 1e12
-                                  if tm["close_ms"] > 0 else 0.0),
-                  "gflop_per_step": tm["close_flops"] / K / 1e9},
+        "energy": e_head,
+        "other_precisions": per_prec,
+        "phases_ms_per_step": {"gates": tm["gates_ms"] / K, "expect": tm["expect_ms"] / K,
+                               "env_kernels": tm["env_ms"] / K, "close_kernels": tm["close_ms"] / K},
+        "close": {"tflops_algorithmic": (tm["close_flops"] / (tm["close_ms"] * 1e-3) / 1e12
+                                         if tm["close_ms"] > 0 else 0.0),
+                  "gflop_per_step_algorithmic": tm["close_flops"] / K / 1e9,
+                  "gflop_per_step_tiles": tm["close_tile_flops"] / K / 1e9,
+                  "note": "algorithmic: 4 D^2 per distinct (prefix, suffix) pair; tiles: every pair of "
+                          "the 64x64 Gram tiles computed"},
         "jacobi_sweeps_per_step": tm["jacobi_sweeps"] / K,
         "jacobi_groups": args.jacobi_groups,
         "jacobi_batch_sweeps_per_step": tm["jacobi_batch_sweeps"] / K,
+        "jacobi_split_batches_per_step": tm["jacobi_split_batches"] / K,
         "expect_phase_by_precision": precisions,
         "plan": st,
         "autotune": autotune_summary(binding, not args.no_autotune),
@@ -449,7 +488,7 @@ def main():
         "roofline_jacobi": roofline_jacobi,
     }
     if not args.no_serving:
-        out["serving"] = serving_sample(args.serving_fragments, args.prec)
+        out["serving"] = serving_sample(args.serving_fragments, "c64")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(w)

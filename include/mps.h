@@ -66,7 +66,8 @@ typedef enum {
  * and each real product is h h' + (h l' + l h') / S with FP32 accumulation
  * (about 16 significant bits for bf16, S = 1; about 22 for f16, S = 2^11,
  * which needs operands bounded by 1, as site tensors and environments are).
- * Their closing traces run in FP32 as for C64. */
+ * For every precision the closing traces Re Tr(L R) accumulate in FP64 (from
+ * FP32 environments for C64 and the split variants). */
 typedef enum {
   MPS_PREC_C128 = 0,       /* complex128 on FP64 MFMA                              */
   MPS_PREC_C64 = 1,        /* complex64 on FP32 MFMA                               */
@@ -237,6 +238,28 @@ mps_status mps_expect_pauli_rows(mps_handle h, mps_pauli_sum p, mps_precision pr
                                  const int64_t* row_ptr, const int64_t* cols, const double* vals,
                                  double* out);
 
+/* E over several plans on one state: the chunks of a Pauli sum whose trie
+ * environments would not fit in device memory at once (each chunk a plan of
+ * its own, same qubit count).  Each plan is evaluated exactly as by
+ * mps_expect_pauli_sum; its compensated (sum, error) pair stays on the
+ * device, and the pairs are added there in plan order with the same
+ * error-free transformations, so the final sum of c_k Re<P_k> over all
+ * chunks (Methods, UCC: the energy from the qubit Hamiltonian's expectation
+ * values) is an FP64 device result read once.  per_term, if not NULL,
+ * receives Re<P_k> of every plan's strings, concatenated in plan order.
+ * MPS_ERR_ARG for n_plans < 1, a NULL plan or a qubit-count mismatch. */
+mps_status mps_expect_pauli_sums(mps_handle h, int32_t n_plans, const mps_pauli_sum* plans,
+                                 mps_precision prec, double* energy, double* per_term);
+
+/* The state as a dense vector (Eq. mps: c_{i_1..i_N} = B^{i_1} ... B^{i_N},
+ * contracted site by site on the device): psi receives 2^N complex
+ * amplitudes as (re, im) pairs, qubit 0 the most significant bit of the
+ * index.  The amplitudes are those of the stored tensors (after truncating
+ * gates the stored state has unit norm up to rounding; no renormalisation).
+ * N <= 26 (1 GiB of amplitudes), else MPS_ERR_ARG.  Allocates two 2^N
+ * device buffers for the duration of the call. */
+mps_status mps_to_statevector(mps_handle h, double* psi);
+
 /* Copy site q's tensor to the host: *dl, *dr receive D_q, D_{q+1}; b (may be
  * NULL) receives 2*D_q*D_{q+1} complex values as (re, im) pairs in
  * [s][alpha][beta] order; lambda_left (may be NULL) receives the D_q
@@ -315,7 +338,8 @@ typedef struct {
   double env_flops;         /* algorithmic FLOPs of those launches (4M complex) */
   int64_t env_updates;      /* transfer-matrix updates performed               */
   double close_ms;          /* summed duration of closing (trace) launches     */
-  double close_flops;       /* algorithmic FLOPs of the closing products       */
+  double close_flops;       /* algorithmic FLOPs of the closing traces: 4 D^2  *
+                             * per distinct (prefix, suffix) pair, Re Tr(L R)  */
   double expect_ms;         /* wall time of mps_expect_pauli_sum calls         */
   double gates_ms;          /* wall time of gate application                   */
   double canon_ms;          /* wall time of canonicalisation                   */
@@ -327,6 +351,12 @@ typedef struct {
                              * env and close figures above cover eager launches */
   int64_t jacobi_batch_sweeps; /* sweeps launched for multi-launch Jacobi batches *
                                 * (a batch runs until its slowest item converges) */
+  int64_t jacobi_multi_items;  /* SVDs that ran as multi-launch rounds (rows of    *
+                                * 129..1024 elements, more than 64 x 64 entries)   */
+  int64_t jacobi_wide_items;   /* of those, SVDs with rows of 513..1024 elements   */
+  int64_t jacobi_split_batches; /* batches whose rounds ran in >= 2 item groups    */
+  double close_tile_flops;     /* FLOPs of the 64 x 64 Gram tiles the closing    *
+                                * launches compute (every pair of a needed tile)  */
 } mps_timing;
 
 mps_status mps_set_timing(mps_handle h, int32_t enabled); /* also resets counters */

@@ -63,6 +63,10 @@ class Timing(C.Structure):
         ("jacobi_flops", C.c_double),
         ("graph_launches", C.c_int64),
         ("jacobi_batch_sweeps", C.c_int64),
+        ("jacobi_multi_items", C.c_int64),
+        ("jacobi_wide_items", C.c_int64),
+        ("jacobi_split_batches", C.c_int64),
+        ("close_tile_flops", C.c_double),
     ]
 
     def as_dict(self):
@@ -108,6 +112,8 @@ _SIGS = {
     "mps_get_timing": [_P, _P],
     "mps_device_bytes": [_P, _P],
     "mps_selftest_mfma": [_P],
+    "mps_expect_pauli_sums": [_P, _I32, _P, C.c_int, _P, _P],
+    "mps_to_statevector": [_P, _P],
 }
 
 
@@ -297,6 +303,21 @@ class Mps:
         out = np.zeros(psum.n_terms, np.float64) if per_term else None
         _check(_lib.mps_expect_pauli_sum(self._h, psum._h, PREC[prec], C.byref(e), _ptr(out)))
         return (e.value, out) if per_term else e.value
+
+    def expect_chunks(self, plans, prec: str = "c128", per_term: bool = False):
+        """E over several plans (chunks of one Pauli sum), summed on the device."""
+        n = len(plans)
+        arr = (C.c_void_p * n)(*[p._h for p in plans])
+        e = C.c_double()
+        out = np.zeros(sum(p.n_terms for p in plans), np.float64) if per_term else None
+        _check(_lib.mps_expect_pauli_sums(self._h, n, arr, PREC[prec], C.byref(e), _ptr(out)))
+        return (e.value, out) if per_term else e.value
+
+    def to_statevector(self) -> np.ndarray:
+        """2^N amplitudes, qubit 0 the most significant bit (N <= 26)."""
+        psi = np.zeros(1 << self.n, np.complex128)
+        _check(_lib.mps_to_statevector(self._h, _ptr(psi.view(np.float64))))
+        return psi
 
     # -- instrumentation ----------------------------------------------------
     def set_fused_gates(self, on: bool = True):

@@ -4,15 +4,14 @@ One plan keeps an environment (D x D) for every prefix and suffix node of its
 tries; at 100 qubits and D = 512 the 2^20 sampled strings need about 2.2e5
 nodes, 470 GB in complex64.  The strings are therefore sorted (so that shared
 prefixes stay together) and cut into chunks of at most `max_strings`; each
-chunk is one plan, evaluated on the same MPS with the same kernels, and the
-chunk energies (each a compensated device sum) are added with math.fsum.
-The per-string values are the same as from one plan up to the rounding order
-of their transfer products.
+chunk is one plan, evaluated on the same MPS with the same kernels by one
+mps_expect_pauli_sums call: each chunk's compensated (sum, error) pair stays
+on the device and the pairs are added there in chunk order.  The per-string
+values are the same as from one plan up to the rounding order of their
+transfer products.
 """
 
 from __future__ import annotations
-
-import math
 
 import numpy as np
 
@@ -39,17 +38,14 @@ class ChunkedPauliSum:
         return [p.stats() for p in self.plans]
 
     def expect(self, m: "binding.Mps", prec: str = "c128", per_term: bool = False):
-        energies = []
-        per = np.zeros(self.n_terms) if per_term else None
-        for p, (a, b) in zip(self.plans, self.bounds):
-            if per_term:
-                e, v = m.expect(p, prec, per_term=True)
-                per[self.order[a:b]] = v
-            else:
-                e = m.expect(p, prec)
-            energies.append(e)
-        e = math.fsum(energies)
-        return (e, per) if per_term else e
+        if not self.plans:
+            return (0.0, np.zeros(0)) if per_term else 0.0
+        if per_term:
+            e, v = m.expect_chunks(self.plans, prec, per_term=True)
+            per = np.zeros(self.n_terms)
+            per[self.order] = v
+            return e, per
+        return m.expect_chunks(self.plans, prec)
 
     def close(self):
         for p in self.plans:

@@ -213,8 +213,14 @@ hipError_t launch_rows(const double* per_term, const int64_t* row_ptr, const int
                        int64_t n_rows, double* out, hipStream_t s);
 hipError_t launch_gather(const double* g, const int64_t* gidx, const double2* nrm, double* per_term,
                          int64_t n, hipStream_t s);
+// out[0], out[1]: compensated (sum, error) pair of sum_k coeffs[k] per_term[k]
 hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n, double* out,
                          hipStream_t s);
+hipError_t launch_pair_sum(const double* pairs, int n, double* out, hipStream_t s);
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_sv_site(const double2* in, const double2* b, double2* out, int64_t amps, int dl, int dr,
+                          hipStream_t s);
 hipError_t launch_selftest_mfma(double* out, hipStream_t s);
 
 }  // namespace mps

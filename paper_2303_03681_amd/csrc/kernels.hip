@@ -1091,6 +1091,56 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t count, hipStream
   return hipGetLastError();
 }
 
+// Zero-fill of a device region (a kernel, not a memset node: callers may
+// capture it in a graph).
+__global__ void zero_kernel(uint64_t* dst, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256)
+    dst[i] = 0;
+}
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s) {
+  const size_t words = (bytes + 7) / 8;
+  if (words == 0) return hipSuccess;
+  size_t blocks = (words + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t*)dst, words);
+  return hipGetLastError();
+}
+
+// One site of the statevector contraction of Eq. (mps):
+//   out[(a, s)][beta] = sum_alpha in[a][alpha] B^s[alpha][beta],
+// `in` holding `amps` rows of D_l amplitudes-with-open-bond, `out` 2 amps rows
+// of D_r.  Row index a is the bit string of the sites already contracted,
+// the earliest site most significant, so qubit 0 ends as the top bit.
+__global__ void sv_site_kernel(const double2* in, const double2* b, double2* out, int64_t amps, int dl,
+                               int dr) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t total = amps * 2 * dr;
+  if (i >= total) return;
+  const int beta = (int)(i % dr);
+  const int64_t as = i / dr;
+  const int sbit = (int)(as & 1);
+  const int64_t a = as >> 1;
+  const double2* row = in + a * dl;
+  const double2* col = b + (size_t)sbit * dl * dr + beta;
+  double re = 0.0, im = 0.0;
+  for (int al = 0; al < dl; ++al) {
+    const double2 x = row[al], y = col[(size_t)al * dr];
+    re += x.x * y.x - x.y * y.y;
+    im += x.x * y.y + x.y * y.x;
+  }
+  out[i] = make_double2(re, im);
+}
+
+hipError_t launch_sv_site(const double2* in, const double2* b, double2* out, int64_t amps, int dl, int dr,
+                          hipStream_t s) {
+  const int64_t total = amps * 2 * dr;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sv_site_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, in, b, out, amps,
+                     dl, dr);
+  return hipGetLastError();
+}
+
 __global__ void fill_ident_kernel(double2* dst, int d) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < d * d) dst[i] = make_double2((i / d) == (i % d) ? 1.0 : 0.0, 0.0);
@@ -1526,7 +1576,30 @@ __global__ __launch_bounds__(1024) void energy_kernel(const double* per_term, co
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = hs[0] + ls[0];
+  if (threadIdx.x == 0) {  // the compensated pair (sum, error); the value is their sum
+    out[0] = hs[0];
+    out[1] = ls[0];
+  }
+}
+
+// Several compensated pairs (hi_i, lo_i), i < n, added in index order with the
+// same error-free transformations: out[0] = sum, out[1] = error.
+__global__ void pair_sum_kernel(const double* pairs, int n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0, c = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double t, e;
+    two_sum(s, pairs[2 * i], t, e);
+    s = t;
+    c += e + pairs[2 * i + 1];
+  }
+  out[0] = s;
+  out[1] = c;
+}
+
+hipError_t launch_pair_sum(const double* pairs, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(64), 0, s, pairs, n, out);
+  return hipGetLastError();
 }
 
 // out[r] = sum_{i in row r} vals[i] <P_{cols[i]}>, one thread per row, with

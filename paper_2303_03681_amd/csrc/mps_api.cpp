@@ -17,6 +17,7 @@
 #include <memory>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -35,6 +36,7 @@ mps_status fail(mps_status st, const std::string& msg) {
   return st;
 }
 
+constexpr int kMaxStatevectorQubits = 26;
 constexpr double kEpsScale = 1.1102230246251565e-16;  // 2^-53: eps = m * 2^-53 (Algorithm 1)
 constexpr double kCanonCutoff = 1e-14;                  // round-off singular values only
 constexpr int kDefaultSweeps = 60;
@@ -125,7 +127,8 @@ struct ExpectSetup {
   size_t rows_bytes = 0;
   size_t gram_off = 0, tiles_off = 0;
   int gram_items = 0, gram_tiles = 0;
-  double gram_flops = 0.0;
+  double gram_flops = 0.0;  // dense tile work of the closing traces
+  double pair_flops = 0.0;  // 4 D^2 per distinct (prefix, suffix) pair
   int64_t n_updates = 0;
 };
 
@@ -190,6 +193,8 @@ struct mps_state {
   size_t desc_bytes = 0;
   double2* d_gates = nullptr;
   size_t gates_cap = 0;
+  double* d_pairs = nullptr;  // compensated energy pairs of mps_expect_pauli_sums
+  size_t pairs_cap = 0;
   std::vector<std::pair<void*, size_t>> allocs;
   ExpectSetup ex;
   // timing
@@ -560,6 +565,9 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
   for (const JacItem& b : jp.wide) is_multi[b.rot - all[0].rot] = 1;
   const int nmulti = nmulti_items;
   const bool timed = h->timing && nmulti > 0;
+  h->tm.jacobi_multi_items += nmulti;
+  h->tm.jacobi_wide_items += (int64_t)jp.wide.size();
+  if (n_groups > 1) h->tm.jacobi_split_batches += 1;
   if (n_groups > 1) {
     if ((st = ensure_jside(h, n_groups)) != MPS_OK) return st;
     HIP_TRY(h, hipEventRecord(h->ev_jfork, h->stream));
@@ -1194,6 +1202,7 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   size_t gtot = 0;
   std::vector<std::vector<const void*>> lptrs, rptrs;
   ex.gram_flops = 0.0;
+  ex.pair_flops = 0.0;
   for (int c = 0; c <= n; ++c) {
     if (by_bond[c].empty()) continue;
     std::unordered_map<int32_t, int> li, ri;
@@ -1208,6 +1217,11 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
       pb.push_back(b.first->second);
     }
     const int nl = (int)lref.size(), nr = (int)rref.size();
+    {  // the method's own work: Re Tr(L R) = 4 D^2 FLOPs per distinct pair
+      std::unordered_set<int64_t> distinct;
+      for (size_t q = 0; q < pa.size(); ++q) distinct.insert((int64_t)pa[q] * nr + pb[q]);
+      ex.pair_flops += 4.0 * (double)distinct.size() * D[c] * D[c];
+    }
     std::vector<int> lpos(nl), rpos(nr);
     for (int i = 0; i < nl; ++i) lpos[i] = i;
     for (int i = 0; i < nr; ++i) rpos[i] = i;
@@ -1300,7 +1314,7 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
     if ((st = dalloc_t(h, &ex.per_term, tc)) != MPS_OK) return st;
     if ((st = dalloc_t(h, &ex.coeffs, tc)) != MPS_OK) return st;
     if ((st = dalloc_t(h, &ex.gidx, tc)) != MPS_OK) return st;
-    if ((st = dalloc_t(h, &ex.energy, 1)) != MPS_OK) return st;
+    if ((st = dalloc_t(h, &ex.energy, 2)) != MPS_OK) return st;  // compensated (sum, error)
     ex.terms_cap = tc;
   }
   // ---- upload the blob
@@ -1494,8 +1508,10 @@ struct RowsSpec {
   double* out;
 };
 
+// pair_out (device, may be null) receives the energy's compensated (sum,
+// error) pair, for sums over several plans added on the device.
 mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
-                       double* per_term, const RowsSpec* rows = nullptr) {
+                       double* per_term, const RowsSpec* rows = nullptr, double* pair_out = nullptr) {
   mps_status st;
   const double t0 = now_ms();
   if ((st = build_expect(h, ps, prec)) != MPS_OK) return st;
@@ -1549,7 +1565,8 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
                            h->stream));
     if (timed) {
       HIP_TRY(h, hipEventRecord(e, h->stream));
-      h->tm.close_flops += ex.gram_flops;
+      h->tm.close_flops += ex.pair_flops;
+      h->tm.close_tile_flops += ex.gram_flops;
     }
     if (!capturing && h->timing) h->tm.env_updates += ex.n_updates;
     HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, nrm, ex.per_term, T, h->stream));
@@ -1595,9 +1612,11 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   } else if ((st = device_sequence(false)) != MPS_OK) {
     return st;
   }
-  double E = 0.0;
+  double E2[2] = {0.0, 0.0};
   double2 nn = make_double2(1.0, 0.0);
-  HIP_TRY(h, hipMemcpyAsync(&E, ex.energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (pair_out)
+    HIP_TRY(h, hipMemcpyAsync(pair_out, ex.energy, 2 * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(E2, ex.energy, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   if (nrm) HIP_TRY(h, hipMemcpyAsync(&nn, nrm, sizeof(double2), hipMemcpyDeviceToHost, h->stream));
   if (per_term && T)
     HIP_TRY(h, hipMemcpyAsync(per_term, ex.per_term, sizeof(double) * T, hipMemcpyDeviceToHost,
@@ -1630,7 +1649,7 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   if (!pending.empty() && (st = finish_tuning(h, pending)) != MPS_OK) return st;
   if (!(nn.x > 0.0) || !std::isfinite(nn.x)) return fail(MPS_ERR_NONFINITE, "state norm is zero or not finite");
   if (nrm) h->norm = std::sqrt(nn.x);
-  *energy = E;
+  *energy = E2[0] + E2[1];
   h->tm.expect_ms += now_ms() - t0;
   return MPS_OK;
 }
@@ -2176,6 +2195,80 @@ mps_status mps_expect_pauli_rows(mps_handle h, mps_pauli_sum p, mps_precision pr
   RowsSpec rs{n_rows, nnz, row_ptr, cols, vals, out};
   double energy = 0.0;
   return expect_impl(h, p, (int)prec, &energy, nullptr, &rs);
+}
+
+mps_status mps_expect_pauli_sums(mps_handle h, int32_t n_plans, const mps_pauli_sum* plans,
+                                 mps_precision prec, double* energy, double* per_term) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (n_plans < 1 || !plans || !energy) return fail(MPS_ERR_ARG, "need n_plans >= 1, plans and energy");
+  for (int32_t i = 0; i < n_plans; ++i) {
+    if (!plans[i]) return fail(MPS_ERR_ARG, "NULL plan");
+    if (plans[i]->plan.n_qubits != h->n) return fail(MPS_ERR_ARG, "plan and MPS qubit counts differ");
+  }
+  if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64 && prec != MPS_PREC_SPLIT_BF16 &&
+      prec != MPS_PREC_SPLIT_F16)
+    return fail(MPS_ERR_ARG, "unknown precision");
+  const size_t need = 2 * (size_t)n_plans + 2;
+  if (need > h->pairs_cap || !h->d_pairs) {
+    if ((st = sync(h)) != MPS_OK) return st;
+    dfree(h, h->d_pairs);
+    h->d_pairs = nullptr;
+    h->pairs_cap = 0;
+    if ((st = dalloc_t(h, &h->d_pairs, need)) != MPS_OK) return st;
+    h->pairs_cap = need;
+  }
+  size_t off = 0;
+  for (int32_t i = 0; i < n_plans; ++i) {
+    double e = 0.0;
+    if ((st = expect_impl(h, plans[i], (int)prec, &e, per_term ? per_term + off : nullptr, nullptr,
+                          h->d_pairs + 2 * (size_t)i)) != MPS_OK)
+      return st;
+    off += (size_t)plans[i]->plan.n_terms;
+  }
+  double* out = h->d_pairs + 2 * (size_t)n_plans;
+  HIP_TRY(h, launch_pair_sum(h->d_pairs, n_plans, out, h->stream));
+  double E2[2] = {0.0, 0.0};
+  HIP_TRY(h, hipMemcpyAsync(E2, out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  *energy = E2[0] + E2[1];
+  return MPS_OK;
+}
+
+mps_status mps_to_statevector(mps_handle h, double* psi) {
+  mps_status st = check_handle(h);
+  if (st != MPS_OK) return st;
+  if (!psi) return fail(MPS_ERR_ARG, "NULL output");
+  if (h->n > kMaxStatevectorQubits)
+    return fail(MPS_ERR_ARG, "statevector limited to " + std::to_string(kMaxStatevectorQubits) + " qubits");
+  // Every partial contraction holds 2^q D_q <= 2^N amplitudes (D_q <= 2^(N-q)).
+  const size_t amps = (size_t)1 << h->n;
+  if ((st = sync(h)) != MPS_OK) return st;
+  double2* buf[2] = {nullptr, nullptr};
+  struct Free {
+    mps_state* h;
+    double2** b;
+    ~Free() {
+      (void)hipStreamSynchronize(h->stream);
+      dfree(h, b[0]);
+      dfree(h, b[1]);
+    }
+  } release{h, buf};
+  if ((st = dalloc_t(h, &buf[0], amps)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &buf[1], amps)) != MPS_OK) return st;
+  const double2 one = make_double2(1.0, 0.0);
+  HIP_TRY(h, hipMemcpyAsync(buf[0], &one, sizeof(double2), hipMemcpyHostToDevice, h->stream));
+  int cur = 0;
+  int64_t rows = 1;
+  for (int q = 0; q < h->n; ++q) {
+    const int dl = h->dims[q], dr = h->dims[q + 1];
+    if (rows * 2 * dr > (int64_t)amps) return fail(MPS_ERR_STATE, "internal: bond dimension above 2^(N-q)");
+    HIP_TRY(h, launch_sv_site(buf[cur], h->cur(q), buf[1 - cur], rows, dl, dr, h->stream));
+    cur = 1 - cur;
+    rows *= 2;
+  }
+  HIP_TRY(h, hipMemcpyAsync(psi, buf[cur], sizeof(double2) * amps, hipMemcpyDeviceToHost, h->stream));
+  return sync(h);
 }
 
 mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,

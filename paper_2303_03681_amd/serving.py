@@ -16,12 +16,13 @@ The loop (Server.run):
   2. advance every admitted request by one chunk of gates in one batched call
      (mps_apply_gates_multi: one device launch per gate index, one workgroup
      per request, so all dependent gate chains move together);
-  3. requests whose gates are done get their energy (canonicalise + Pauli-sum
-     expectation) between chunks;
+  3. requests whose gates are done get their energy (the Pauli-sum
+     expectation from the boundary environments, divided by <psi|psi>; no
+     canonicalisation sweep) between chunks;
   4. finished requests free their slot; arrivals are admitted between chunks.
 
 Energies run between gate chunks rather than beside them: the expectation
-and canonicalisation paths synchronise with the host many times, and streams
+path synchronises with the host many times, and streams
 beyond the device's few hardware queues share a queue in submission order, so
 each of those waits could otherwise stall behind a whole gate chunk.  Chunks
 are sized to a target duration so that arrivals wait at most about that long

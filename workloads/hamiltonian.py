@@ -214,6 +214,18 @@ def _two_body_chunk(args):
     return _reduce(k2, v2)
 
 
+_WORKER: dict = {}
+
+
+def _init_two_body(g, words):
+    _WORKER["g"] = g
+    _WORKER["words"] = words
+
+
+def _two_body_worker(p0):
+    return _two_body_chunk((p0, _WORKER["g"], _WORKER["words"]))
+
+
 def jw_hamiltonian(h: np.ndarray, g: np.ndarray, drop_rel: float = 1e-15,
                    workers: int | None = None, progress=None) -> PauliSum:
     """Jordan-Wigner Pauli sum of the spin-orbital Hamiltonian built from (h, g).
@@ -243,11 +255,14 @@ def jw_hamiltonian(h: np.ndarray, g: np.ndarray, drop_rel: float = 1e-15,
     args = [(p0, g, words) for p0 in range(n_s)]
     say = progress or (lambda msg: None)
     if workers > 1:
+        # fresh interpreters ("spawn"), not forks: the caller may already hold
+        # a GPU context, which a forked child must not inherit
         import multiprocessing as mp
         from concurrent.futures import ProcessPoolExecutor
         parts = []
-        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
-            for i, part in enumerate(ex.map(_two_body_chunk, args)):
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                                 initializer=_init_two_body, initargs=(g, words)) as ex:
+            for i, part in enumerate(ex.map(_two_body_worker, range(n_s))):
                 parts.append(part)
                 say(f"two-body chunk {i + 1}/{n_s}")
     else:
