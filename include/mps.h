@@ -285,6 +285,23 @@ mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, cons
 mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors, double* sigma,
                           double* out_vectors, int32_t* sweeps);
 
+/* mps_jacobi_svd for callers that cannot allocate device memory (code
+ * running under stream capture, tight serving loops, hosts that forbid
+ * hipMalloc): same arguments, same kernels, same results, but every device
+ * buffer -- the work and output vectors, norms, rotation counters, sigma and
+ * launch descriptors -- lives in a fixed scratch array that the library
+ * holds on each device it runs on until the process ends (about 8.1 MiB).
+ * It calls no hipMalloc/hipFree and creates no stream: the work is enqueued
+ * on `stream` (a hipStream_t; NULL = the null stream), which the call
+ * synchronises before it returns.  Limits: 1 <= n_vec <= 512 and
+ * 1 <= vec_len <= 512 (one 512 x 512 complex matrix), MPS_ERR_ARG beyond.
+ * Every call on one device shares that device's scratch and keeps the last
+ * call's contents (the call clears what it accumulates): calls that overlap
+ * on one device, from several threads or streams, race and must be
+ * serialised by the caller. */
+mps_status mps_jacobi_svd_noalloc(int32_t n_vec, int32_t vec_len, const double* vectors, double* sigma,
+                                  double* out_vectors, int32_t* sweeps, void* stream);
+
 /* Tile autotuning of the environment-update GEMMs (c128 and c64; the split
  * precisions keep their one tile).  With `enabled` != 0, the first
  * mps_expect_pauli_sum of this handle that meets a launch class without a

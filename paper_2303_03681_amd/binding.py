@@ -114,6 +114,7 @@ _SIGS = {
     "mps_selftest_mfma": [_P],
     "mps_expect_pauli_sums": [_P, _I32, _P, C.c_int, _P, _P],
     "mps_to_statevector": [_P, _P],
+    "mps_jacobi_svd_noalloc": [_I32, _I32, _P, _P, _P, _P, _P],
 }
 
 
@@ -415,6 +416,20 @@ def jacobi_svd(vectors: np.ndarray):
     sw = C.c_int32()
     _check(lib.mps_jacobi_svd(n, m, _ptr(v.view(np.float64)), _ptr(sig),
                               _ptr(out.view(np.float64)), C.byref(sw)))
+    return sig, out, sw.value
+
+
+def jacobi_svd_noalloc(vectors: np.ndarray, stream: int | None = None):
+    """As jacobi_svd, through the entry point that allocates no device memory
+    (fixed per-device scratch; at most 512 vectors of at most 512 elements)."""
+    lib = load()
+    v = _cplx(vectors)
+    n, m = v.shape
+    sig = np.zeros(n, np.float64)
+    out = np.zeros((n, m), np.complex128)
+    sw = C.c_int32()
+    _check(lib.mps_jacobi_svd_noalloc(n, m, _ptr(v.view(np.float64)), _ptr(sig),
+                                      _ptr(out.view(np.float64)), C.byref(sw), stream))
     return sig, out, sw.value
 
 

@@ -218,6 +218,16 @@ hipError_t launch_energy(const double* per_term, const double* coeffs, int64_t n
                          hipStream_t s);
 hipError_t launch_pair_sum(const double* pairs, int n, double* out, hipStream_t s);
 
+// Fixed device scratch (a static device array, one per device) for the entry
+// point that allocates nothing: *out receives the current device's address
+// of it (looked up once per device).  Sized for one Jacobi SVD of up to
+// kScratchMaxVec vectors of up to kScratchMaxVec elements.
+constexpr int kScratchMaxVec = 512;
+constexpr size_t kScratchMatBytes = (size_t)kScratchMaxVec * kScratchMaxVec * 16;  // one complex matrix
+constexpr size_t kScratchDescBytes = (size_t)64 << 10;                             // launch descriptors
+constexpr size_t kScratchMiscBytes = (size_t)64 << 10;                             // norms, counters, sigma
+constexpr size_t kScratchBytes = 2 * kScratchMatBytes + kScratchDescBytes + kScratchMiscBytes;
+hipError_t scratch_address(void** out);
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_sv_site(const double2* in, const double2* b, double2* out, int64_t amps, int dl, int dr,
                           hipStream_t s);

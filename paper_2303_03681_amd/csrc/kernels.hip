@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "gemm_core.h"
 #include "gemm_split.h"
@@ -1089,6 +1090,39 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t count, hipStream
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, count);
   return hipGetLastError();
+}
+
+// =================================================================== fixed scratch
+
+// Device scratch of the entry point that allocates nothing
+// (mps_jacobi_svd_noalloc).  Each device holds its own copy of the array at
+// its own address; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept.  Every call on a device shares its copy.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 // Zero-fill of a device region (a kernel, not a memset node: callers may

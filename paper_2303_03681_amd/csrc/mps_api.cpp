@@ -2391,6 +2391,83 @@ mps_status mps_jacobi_svd(int32_t n_vec, int32_t vec_len, const double* vectors,
   return MPS_OK;
 }
 
+mps_status mps_jacobi_svd_noalloc(int32_t n_vec, int32_t vec_len, const double* vectors, double* sigma,
+                                  double* out_vectors, int32_t* sweeps, void* stream) {
+  if (n_vec < 1 || n_vec > kScratchMaxVec || vec_len < 1 || vec_len > kScratchMaxVec || !vectors || !sigma)
+    return fail(MPS_ERR_ARG, "need 1 <= n_vec <= " + std::to_string(kScratchMaxVec) + ", 1 <= vec_len <= " +
+                                 std::to_string(kScratchMaxVec) + " and non-NULL arrays");
+  if (!finite_all(vectors, 2 * (size_t)n_vec * vec_len))
+    return fail(MPS_ERR_NONFINITE, "non-finite input");
+  void* base = nullptr;
+  HIP_TRY(nullptr, scratch_address(&base));
+  mps_state tmp;  // host-side bookkeeping only: no device allocation below
+  tmp.n = 1;
+  tmp.stream = (hipStream_t)stream;
+  tmp.own_stream = false;
+  tmp.max_sweeps = kDefaultSweeps * 2;
+  mps_state* h = &tmp;
+  mps_status st = ensure_lds(h);
+  if (st != MPS_OK) return st;
+  // scratch layout: the work matrix, the output vectors, descriptors, then
+  // small values (all offsets multiples of 256 bytes)
+  char* p = (char*)base;
+  const int m = vec_len + (vec_len & 1);  // even length: finalize splits rows in halves
+  double2* w = (double2*)p;
+  double2* out = (double2*)(p + kScratchMatBytes);
+  h->d_desc = p + 2 * kScratchMatBytes;
+  h->desc_bytes = kScratchDescBytes;
+  char* misc = p + 2 * kScratchMatBytes + kScratchDescBytes;
+  double* fro2 = (double*)misc;
+  double* scale = (double*)(misc + 256);
+  double* disc = (double*)(misc + 512);
+  int* k = (int*)(misc + 768);
+  int* status = (int*)(misc + 1024);
+  int* sw = (int*)(misc + 1280);
+  int* rot = (int*)(misc + 1536);  // max_sweeps counters
+  double* lam = (double*)(misc + 2048);
+  static_assert(2048 + sizeof(double) * kScratchMaxVec <= kScratchMiscBytes, "misc scratch too small");
+  static_assert(1536 + sizeof(int) * kDefaultSweeps * 2 <= 2048, "rotation counters overlap sigma");
+  // the previous call's contents stay: clear what accumulates or is padded
+  HIP_TRY(h, launch_zero(w, sizeof(double2) * (size_t)n_vec * m, h->stream));
+  HIP_TRY(h, launch_zero(misc, 2048, h->stream));
+  HIP_TRY(h, hipMemcpy2DAsync(w, sizeof(double2) * m, vectors, sizeof(double2) * vec_len,
+                              sizeof(double2) * vec_len, n_vec, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, launch_fro2(w, n_vec * m, fro2, h->stream));
+  std::vector<int> swp;
+  std::vector<JacItem> jc{JacItem{w, fro2, rot, sw, n_vec, m, 0, 0, 1}};
+  if ((st = run_jacobi(h, jc, 0, swp)) != MPS_OK) return st;
+  if (swp[0] < 0) return fail(MPS_ERR_NOCONV, "Jacobi SVD did not converge");
+  FinItem fi{w, out, lam, k, scale, disc, status, n_vec, m, n_vec, 0.0, FIN_GATE};
+  if ((st = upload(h, h->d_desc, &fi, sizeof(fi))) != MPS_OK) return st;
+  HIP_TRY(h, launch_finalize((const FinItem*)h->d_desc, 1, h->stream));
+  int kk = 0, stt = 0;
+  double sc = 0.0;
+  HIP_TRY(h, hipMemcpyAsync(&kk, k, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&stt, status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&sc, scale, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if ((st = sync(h)) != MPS_OK) return st;
+  if (kk < 0 || kk > n_vec) return fail(MPS_ERR_STATE, "internal: kept rank out of range");
+  // sigma: lam holds sigma / ||sigma|| for the kept (= all nonzero) values
+  HIP_TRY(h, hipMemcpyAsync(sigma, lam, sizeof(double) * kk, hipMemcpyDeviceToHost, h->stream));
+  if (out_vectors) {
+    // finalize writes the vectors as [s][a][r], each row split at m / 2
+    const int half = m / 2;
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int width = s2 == 0 ? std::min(half, vec_len) : vec_len - half;
+      if (width <= 0 || kk == 0) continue;
+      HIP_TRY(h, hipMemcpy2DAsync(out_vectors + 2 * (size_t)s2 * half, sizeof(double2) * vec_len,
+                                  out + (size_t)s2 * kk * half, sizeof(double2) * half,
+                                  sizeof(double2) * width, kk, hipMemcpyDeviceToHost, h->stream));
+    }
+  }
+  if ((st = sync(h)) != MPS_OK) return st;
+  for (int a = 0; a < n_vec; ++a) sigma[a] = (a < kk && sc > 0.0) ? sigma[a] / sc : 0.0;
+  if (out_vectors && kk < n_vec)
+    std::memset(out_vectors + 2 * (size_t)kk * vec_len, 0, sizeof(double) * 2 * (size_t)(n_vec - kk) * vec_len);
+  if (sweeps) *sweeps = swp[0];
+  return MPS_OK;
+}
+
 mps_status mps_set_jacobi_groups(mps_handle h, int32_t groups) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;
