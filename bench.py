@@ -38,7 +38,7 @@ PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}  # MI355X dense FP64 / FP32 matrix pe
 # HBM bytes per environment launch on this workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by a 256 MiB copy), environment kernels
 # unchanged since; profiles/env_gemm_traffic_50q_D256.md has the commands and figures.
-ENV_TRAFFIC_BYTES = {"c64": 444.5e6, "c128": None, "split_bf16": 429.0e6, "split_f16": 429.0e6}
+ENV_TRAFFIC_BYTES = {"c64": 444.5e6, "c128": 996.9e6, "split_bf16": 429.0e6, "split_f16": 429.0e6}
 METRIC = "Pauli-string expectations/s at 50q D=256 vs complex128 path; p50/p99 latency"
 
 
@@ -285,6 +285,9 @@ def main():
     ap.add_argument("--other-precisions", default="c64,split_f16,split_bf16",
                     help="precisions timed over the same K steps after the headline ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the warmup and the K headline steps (for kernel profiles): no other "
+                         "precisions, expectation-phase sweep, samples or CPU baseline")
     ap.add_argument("--layers", type=int, default=None, help="override (smaller) layer count")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix sample")
     ap.add_argument("--no-extras", action="store_true",
@@ -298,6 +301,9 @@ def main():
                     help="first copy MIB MiB device-to-device three times (a plain copy of known "
                          "size for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.headline_only:
+        args.other_precisions = ""
+        args.no_serving = args.no_extras = args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no multi-GPU "
               f"path; the Pauli strings would shard across GPUs by trie subtree.", file=sys.stderr)
@@ -399,7 +405,7 @@ def main():
 
     # expectation phase alone on the final state, every precision
     precisions = {}
-    for pr in ("c128", "c64", "split_bf16", "split_f16"):
+    for pr in (("c128", "c64", "split_bf16", "split_f16") if not args.headline_only else (args.prec,)):
         m.expect(plan, pr)  # setup for this precision (untimed)
         m.set_timing(True)
         torch.cuda.synchronize()
@@ -420,7 +426,7 @@ def main():
         }
     graphs = None if args.no_extras else graph_sample(binding, torch, stream, m, plan)
     grad_sample = None if args.no_extras else gradient_sample(binding, stream)
-    e_ref = precisions["c128"]["energy"]
+    e_ref = precisions["c128"]["energy"] if "c128" in precisions else e_head
     for pr, d in precisions.items():
         d["abs_dE_vs_c128"] = abs(d["energy"] - e_ref)
         log(f"expect {pr}: {d['expect_ms']:.1f} ms, env {d['env_tflops_algorithmic']:.1f} TFLOP/s, "

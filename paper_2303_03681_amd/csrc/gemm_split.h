@@ -16,7 +16,8 @@
 //
 // The problem functors are those of cgemm_kernel (gemm_core.h) with T = float;
 // the tile loop, XCD remap and operand handles follow cgemm_kernel, with the
-// split done when a staged FP32 tile is written to LDS.
+// split done when a staged FP32 tile is written to LDS (8 consecutive k per
+// thread, each 16-bit plane stored as one 16-byte vector).
 //
 // MFMA 16x16x32 operand layout (wave64), lane l, j = 0..7:
 //   A fragment A[l % 16][8 (l / 16) + j], B fragment B[8 (l / 16) + j][l % 16],
@@ -71,11 +72,8 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
   constexpr int BK = 32;
   constexpr int KP = BK + 8;  // LDS row length (16-bit values): rows stay 16-byte aligned
   constexpr int NT = 256;
-  constexpr int A_EL = BM * BK / NT;
-  constexpr int B_EL = BK * BN / NT;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(A_EL * NT == BM * BK && B_EL * NT == BK * BN, "tile/threads");
 
   // [0] leading real, [1] leading imaginary, [2] trailing real, [3] trailing imaginary
   __shared__ __attribute__((aligned(16))) L As[4][BM][KP];
@@ -102,70 +100,52 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
   const int lr = lane & 15;
   const int lk = lane >> 4;
 
-  C2 ra[A_EL], rb[B_EL];
-  typename P::RowA ha[A_EL];
-  typename P::ColB hb[B_EL];
-  auto a_coord = [&](int e, int& ii, int& kk) {
-    const int idx = tid + e * NT;
-    if (P::A_CONTIG_K) { kk = idx % BK; ii = idx / BK; }
-    else { ii = idx % BM; kk = idx / BM; }
-  };
-  auto b_coord = [&](int e, int& kk, int& jj) {
-    const int idx = tid + e * NT;
-    if (P::B_CONTIG_N) { jj = idx % BN; kk = idx / BN; }
-    else { kk = idx % BK; jj = idx / BK; }
-  };
-#pragma unroll
-  for (int e = 0; e < A_EL; ++e) {
-    int ii, kk;
-    a_coord(e, ii, kk);
-    if (m0 + ii < M) ha[e] = P::rowA(ctx, m0 + ii);
-  }
-#pragma unroll
-  for (int e = 0; e < B_EL; ++e) {
-    int kk, jj;
-    b_coord(e, kk, jj);
-    if (n0 + jj < N) hb[e] = P::colB(ctx, n0 + jj);
-  }
+  // Staging: each thread moves 8 consecutive k of one row of A and one
+  // column of B.  The operand's contiguous index runs across neighbouring
+  // threads (so global loads coalesce), and each of the four 16-bit planes of
+  // the 8 values goes to LDS as one 16-byte store.
+  constexpr int KC = BK / 8;
+  static_assert(BM * KC == NT && BN * KC == NT, "one row (column) and 8 k per thread");
+  const int a_i = P::A_CONTIG_K ? tid / KC : tid % BM;
+  const int a_k = 8 * (P::A_CONTIG_K ? tid % KC : tid / BM);
+  const int b_j = P::B_CONTIG_N ? tid % BN : tid / KC;
+  const int b_k = 8 * (P::B_CONTIG_N ? tid / BN : tid % KC);
+  C2 ra[8], rb[8];
+  typename P::RowA ha{};
+  typename P::ColB hb{};
+  if (m0 + a_i < M) ha = P::rowA(ctx, m0 + a_i);
+  if (n0 + b_j < N) hb = P::colB(ctx, n0 + b_j);
   auto load_tiles = [&](int k0) {
+    const int gi = m0 + a_i, gj = n0 + b_j;
 #pragma unroll
-    for (int e = 0; e < A_EL; ++e) {
-      int ii, kk;
-      a_coord(e, ii, kk);
-      const int gi = m0 + ii, gk = k0 + kk;
-      C2 v = make_float2(0.f, 0.f);
-      if (gi < M && gk < K) v = P::loadA(ctx, ha[e], gi, gk);
-      ra[e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < B_EL; ++e) {
-      int kk, jj;
-      b_coord(e, kk, jj);
-      const int gk = k0 + kk, gj = n0 + jj;
-      C2 v = make_float2(0.f, 0.f);
-      if (gk < K && gj < N) v = P::loadB(ctx, hb[e], gk, gj);
-      rb[e] = v;
+    for (int j = 0; j < 8; ++j) {
+      const int ga = k0 + a_k + j, gb = k0 + b_k + j;
+      ra[j] = (gi < M && ga < K) ? P::loadA(ctx, ha, gi, ga) : make_float2(0.f, 0.f);
+      rb[j] = (gb < K && gj < N) ? P::loadB(ctx, hb, gb, gj) : make_float2(0.f, 0.f);
     }
   };
-  auto split = [](float x, L& h, L& l) {
-    h = (L)x;
-    l = (L)((x - (float)h) * Tr::S);
+  auto split8 = [](const C2 (&v)[8], V8& rh, V8& ih, V8& rl, V8& il) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const L hr0 = (L)v[j].x, hi0 = (L)v[j].y;
+      rh[j] = hr0;
+      ih[j] = hi0;
+      rl[j] = (L)((v[j].x - (float)hr0) * Tr::S);
+      il[j] = (L)((v[j].y - (float)hi0) * Tr::S);
+    }
   };
   auto store_tiles = [&]() {
-#pragma unroll
-    for (int e = 0; e < A_EL; ++e) {
-      int ii, kk;
-      a_coord(e, ii, kk);
-      split(ra[e].x, As[0][ii][kk], As[2][ii][kk]);
-      split(ra[e].y, As[1][ii][kk], As[3][ii][kk]);
-    }
-#pragma unroll
-    for (int e = 0; e < B_EL; ++e) {
-      int kk, jj;
-      b_coord(e, kk, jj);
-      split(rb[e].x, Bs[0][jj][kk], Bs[2][jj][kk]);
-      split(rb[e].y, Bs[1][jj][kk], Bs[3][jj][kk]);
-    }
+    V8 p0, p1, p2, p3;
+    split8(ra, p0, p1, p2, p3);
+    *(V8*)&As[0][a_i][a_k] = p0;
+    *(V8*)&As[1][a_i][a_k] = p1;
+    *(V8*)&As[2][a_i][a_k] = p2;
+    *(V8*)&As[3][a_i][a_k] = p3;
+    split8(rb, p0, p1, p2, p3);
+    *(V8*)&Bs[0][b_j][b_k] = p0;
+    *(V8*)&Bs[1][b_j][b_k] = p1;
+    *(V8*)&Bs[2][b_j][b_k] = p2;
+    *(V8*)&Bs[3][b_j][b_k] = p3;
   };
 
   f4_t hr[FM][FN], hi[FM][FN], xr[FM][FN], xi[FM][FN];  // leading / cross accumulators
