@@ -183,24 +183,25 @@ def build_config_cached(i):
     return build_config(i, with_gates=False)
 
 
-def serving_sample(n_fragments: int, prec: str) -> dict:
-    """A bounded sample of the serving mix: DMET-like fragments (windowed
-    UCCSD, own random-integral Hamiltonians) arriving as a Poisson stream at
-    200 requests/s, served by the continuous-batching loop; latency p50/p99
-    and throughput, plus one request re-run alone (its energy must match)."""
+def serving_sample(n_fragments: int, prec: str, n_updates: int = 1, qubits=(12, 16, 20),
+                   bonds=(16, 32)) -> dict:
+    """A sample of the serving mix: DMET-like fragments (windowed UCCSD, own
+    random-integral Hamiltonians) arriving as a Poisson stream at 200
+    requests/s, served by the continuous-batching loop; latency p50/p99 and
+    throughput, plus one request re-run alone (its energy must match)."""
     from paper_2303_03681_amd.serving import Fragment, GpuBackend, Request, Server, make_requests
     from workloads import build_serving_fragments
 
     t0 = time.perf_counter()
-    qubits, bonds = (12, 16, 20), (16, 32)
-    raw = build_serving_fragments(n_fragments, 1, qubits=qubits, bonds=bonds)
+    qubits, bonds = tuple(qubits), tuple(bonds)
+    raw = build_serving_fragments(n_fragments, n_updates, qubits=qubits, bonds=bonds)
     frags = [Fragment.from_dict(d) for d in raw]
     log(f"serving sample: {n_fragments} fragments built in {time.perf_counter() - t0:.1f} s")
-    reqs = make_requests(n_fragments, 1, rate=200.0, rng=np.random.default_rng([230303681, 4, 3]))
+    reqs = make_requests(n_fragments, n_updates, rate=200.0, rng=np.random.default_rng([230303681, 4, 3]))
     be = GpuBackend(prec=prec)
     srv = Server(frags, be, max_active=64, chunk=64, chunk_s=1.0,
                  log=lambda m: log("  serving " + m))
-    rep = srv.run(reqs, timeout_s=600)
+    rep = srv.run(reqs, timeout_s=1800)
     srv.close()
     out = rep.summary()
     # the largest fragment alone: same energy as in the mix
@@ -229,7 +230,9 @@ def serving_sample(n_fragments: int, prec: str) -> dict:
     plan.close()
     out.update({
         "workload": (f"{n_fragments} fragments, qubits in {list(qubits)}, D in {list(bonds)}, "
-                     "windowed UCCSD, cutoff 1e-10, Poisson arrivals 200/s, one update each"),
+                     f"windowed UCCSD, cutoff 1e-10, Poisson arrivals 200/s, {n_updates} update(s) each"),
+        "offered_requests_per_s": 200.0,
+        "fragments_by_qubits_and_D": sorted([(f.n_qubits, f.max_bond) for f in frags]),
         "gates_per_request_mean": float(np.mean([len(f.updates[0][0]) for f in frags])),
         "alone_vs_mix": {"fragment": big.fid, "latency_alone_s": alone.latency,
                          "abs_dE": abs(alone.energy - e_mix)},
@@ -297,6 +300,9 @@ def main():
     ap.add_argument("--jacobi-groups", type=int, default=2,
                     help="streams over which the batched gate SVD rounds are split (1 = none)")
     ap.add_argument("--serving-fragments", type=int, default=8)
+    ap.add_argument("--serving-c4", action="store_true",
+                    help="serving sample at the serving mix's own sizes instead of the small one: "
+                         "16 fragments x 3 updates, 12..40 qubits, D in {32, 64, 128} (minutes)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy of known "
                          "size for scaling hardware byte counters)")
@@ -493,7 +499,9 @@ def main():
         "roofline": roofline,
         "roofline_jacobi": roofline_jacobi,
     }
-    if not args.no_serving:
+    if args.serving_c4:
+        out["serving"] = serving_sample(16, "c64", n_updates=3, qubits=range(12, 41, 4), bonds=(32, 64, 128))
+    elif not args.no_serving:
         out["serving"] = serving_sample(args.serving_fragments, "c64")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")

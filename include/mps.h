@@ -122,16 +122,21 @@ mps_status mps_apply_gates(mps_handle h, int64_t n, const int32_t* q0, const int
 
 /* Apply one gate list to each of n_handles distinct MPSs (handles[i] gets
  * n_gates[i] gates from q0[i], q1[i], u_packed[i], laid out as for
- * mps_apply_gates) in one sequence of device launches on `stream` (a
- * hipStream_t; NULL = the first handle's stream): launch s applies gate s of
- * every list, one workgroup per MPS, so the dependent gate chains of several
- * MPSs advance together and share the device (the batching of concurrent
- * requests).  Every two-qubit gate must satisfy the fused-path limit of
- * mps_apply_gates (both outer bond capacities <= 64), else MPS_ERR_ARG and
- * nothing is applied.  Each list is applied exactly as mps_apply_gates'
- * fused path would; a failed gate (NOCONV, NONFINITE) stops only its own
- * list, n_done[i] (may be NULL) receives the gates applied to handle i, and
- * the first failure in handle order is returned.  Synchronises `stream` and
+ * mps_apply_gates) so that the dependent gate chains of several MPSs advance
+ * together and share the device (the batching of concurrent requests).
+ * When every two-qubit gate satisfies the fused-path limit of
+ * mps_apply_gates (both outer bond capacities <= 64), one sequence of device
+ * launches on `stream` (a hipStream_t; NULL = the first handle's stream)
+ * applies gate s of every list at launch s, one workgroup per MPS, exactly
+ * as mps_apply_gates' fused path would.  Otherwise step s applies gate s of
+ * every list as one batched step on the first handle's stream: the
+ * one-qubit gates, then all two-qubit gates of the step -- on distinct MPSs,
+ * hence independent -- as one batch of the multi-workgroup path (one batched
+ * contraction, Jacobi SVD and site update; Eqs. C, C~, svd, Bl), the same
+ * arithmetic as mps_apply_gates' batched path up to the rotation order of
+ * small SVDs.  A failed gate (NOCONV, NONFINITE) stops only its own list,
+ * n_done[i] (may be NULL) receives the gates applied to handle i, and the
+ * first failure in handle order is returned.  Synchronises `stream` and
  * every handle's stream. */
 mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* handles,
                                  const int64_t* n_gates, const int32_t* const* q0,

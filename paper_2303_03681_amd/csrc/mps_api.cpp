@@ -167,6 +167,7 @@ struct mps_state {
   double* d_one = nullptr;
   // gate workspaces
   int ws_items = 0;
+  int ctr_items = 0;  // per-item SVD counters allocated (fro2, rot, sweeps, k, scale, disc, status)
   size_t ws_stride = 0;  // complex elements per item
   double2* ws_c = nullptr;
   double2* ws_w = nullptr;
@@ -344,20 +345,18 @@ mps_status ensure_desc(mps_state* h, size_t bytes) {
 }
 
 // Gate workspaces for up to `items` two-qubit gates at the handle's largest size.
-mps_status ensure_ws(mps_state* h, int items) {
-  if (items <= h->ws_items) return MPS_OK;
+// Per-item counters of a batched SVD (the rotation counters laid out
+// [sweep][item]) for up to `items` gates.
+mps_status ensure_counters(mps_state* h, int items) {
+  if (items <= h->ctr_items) return MPS_OK;
   mps_status st = sync(h);
   if (st != MPS_OK) return st;
-  for (void* p : {(void*)h->ws_c, (void*)h->ws_w, (void*)h->d_fro2, (void*)h->d_rot,
-                  (void*)h->d_sweeps, (void*)h->d_k, (void*)h->d_scale, (void*)h->d_disc,
-                  (void*)h->d_status})
+  for (void* p : {(void*)h->d_fro2, (void*)h->d_rot, (void*)h->d_sweeps, (void*)h->d_k, (void*)h->d_scale,
+                  (void*)h->d_disc, (void*)h->d_status})
     dfree(h, p);
-  int dmax = 1;
-  for (int b = 0; b <= h->n; ++b) dmax = std::max(dmax, h->cap[b]);
-  h->ws_stride = (size_t)(2 * dmax) * (2 * dmax);
-  h->ws_items = 0;
-  if ((st = dalloc_t(h, &h->ws_c, h->ws_stride * items)) != MPS_OK) return st;
-  if ((st = dalloc_t(h, &h->ws_w, h->ws_stride * items)) != MPS_OK) return st;
+  h->d_fro2 = h->d_scale = h->d_disc = nullptr;
+  h->d_rot = h->d_sweeps = h->d_k = h->d_status = nullptr;
+  h->ctr_items = 0;
   if ((st = dalloc_t(h, &h->d_fro2, items)) != MPS_OK) return st;
   if ((st = dalloc_t(h, &h->d_rot, (size_t)items * h->max_sweeps)) != MPS_OK) return st;
   if ((st = dalloc_t(h, &h->d_sweeps, items)) != MPS_OK) return st;
@@ -365,6 +364,25 @@ mps_status ensure_ws(mps_state* h, int items) {
   if ((st = dalloc_t(h, &h->d_scale, items)) != MPS_OK) return st;
   if ((st = dalloc_t(h, &h->d_disc, items)) != MPS_OK) return st;
   if ((st = dalloc_t(h, &h->d_status, items)) != MPS_OK) return st;
+  h->ctr_items = items;
+  return MPS_OK;
+}
+
+// Gate workspaces (C and the Jacobi matrix) for up to `items` two-qubit gates
+// at the handle's largest size, and their counters.
+mps_status ensure_ws(mps_state* h, int items) {
+  mps_status st = ensure_counters(h, items);
+  if (st != MPS_OK || items <= h->ws_items) return st;
+  if ((st = sync(h)) != MPS_OK) return st;
+  dfree(h, h->ws_c);
+  dfree(h, h->ws_w);
+  h->ws_c = h->ws_w = nullptr;
+  int dmax = 1;
+  for (int b = 0; b <= h->n; ++b) dmax = std::max(dmax, h->cap[b]);
+  h->ws_stride = (size_t)(2 * dmax) * (2 * dmax);
+  h->ws_items = 0;
+  if ((st = dalloc_t(h, &h->ws_c, h->ws_stride * items)) != MPS_OK) return st;
+  if ((st = dalloc_t(h, &h->ws_w, h->ws_stride * items)) != MPS_OK) return st;
   if (!h->d_carry[0]) {
     for (int i = 0; i < 2; ++i)
       if ((st = dalloc_t(h, &h->d_carry[i], (size_t)dmax * dmax)) != MPS_OK) return st;
@@ -685,10 +703,35 @@ mps_status run_jacobi(mps_state* h, const std::vector<JacItem>& all, size_t desc
 // ----------------------------------------------------------------------------
 // two-qubit gates (Eqs. C, C~, svd, Bl), one batch of disjoint bonds
 
-mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::vector<int>& gidx) {
-  const int items = (int)qs.size();
-  mps_status st = ensure_ws(h, items);
+// One two-qubit gate of a batch: the handle whose sites (q, q+1) it updates
+// and its 4x4 matrix on the device.
+struct GateRef {
+  mps_state* h;
+  int q;
+  const double2* u;
+};
+
+// Eqs. (C), (C~), (svd), (Bl) for gates on disjoint bonds, possibly of several
+// handles (whose streams are idle): one batched contraction, one batched
+// Jacobi SVD and one batched site update.  Counters, descriptors and launches
+// are the driver's (on its stream); each gate works in its own handle's
+// workspace.  Results go to spare buffers.  all_or_nothing: any failed gate
+// fails the call and nothing is committed (the single-handle contract);
+// otherwise the gates that succeeded are committed and err[b] / msg[b] report
+// the failed ones (their handles unchanged).
+mps_status apply_2q_refs(mps_state* drv, const std::vector<GateRef>& g, bool all_or_nothing,
+                         std::vector<mps_status>& err, std::vector<std::string>& msg) {
+  const int items = (int)g.size();
+  err.assign(items, MPS_OK);
+  msg.assign(items, std::string());
+  mps_status st = ensure_counters(drv, items);
   if (st != MPS_OK) return st;
+  std::vector<int> slot(items, 0);
+  for (int b = 0; b < items; ++b) {
+    for (int c = 0; c < b; ++c)
+      if (g[c].h == g[b].h) ++slot[b];
+    if ((st = ensure_ws(g[b].h, slot[b] + 1)) != MPS_OK) return st;
+  }
   std::vector<ThetaItem> th(items);
   std::vector<MixItem> mx(items);
   std::vector<JacItem> jc(items);
@@ -696,21 +739,22 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
   std::vector<TruncItem> tr(items);
   int max_rows = 0, max_cols = 0, max_dldr = 0, max_k = 0;
   for (int b = 0; b < items; ++b) {
-    const int q = qs[b];
+    mps_state* h = g[b].h;
+    const int q = g[b].q;
     const int dl = h->dims[q], dm = h->dims[q + 1], dr = h->dims[q + 2];
     if ((size_t)(2 * dl) * (2 * dr) > h->ws_stride)
       return fail(MPS_ERR_STATE, "internal: workspace too small");
-    double2* c = h->ws_c + (size_t)b * h->ws_stride;
-    double2* w = h->ws_w + (size_t)b * h->ws_stride;
+    double2* c = h->ws_c + (size_t)slot[b] * h->ws_stride;
+    double2* w = h->ws_w + (size_t)slot[b] * h->ws_stride;
     const int capk = std::min(h->cap[q + 1], std::min(2 * dl, 2 * dr));
     th[b] = ThetaItem{h->cur(q), h->cur(q + 1), c, dl, dm, dr};
-    mx[b] = MixItem{c, w, h->lcur(q), h->d_gates + (size_t)gidx[b] * 16, h->d_fro2 + b, dl, dr};
-    jc[b] = JacItem{w, h->d_fro2 + b, h->d_rot + b, h->d_sweeps + b, 2 * dl, 2 * dr, 0, 0, items};
-    fn[b] = FinItem{w, h->spare(q + 1), h->lspare(q + 1), h->d_k + b, h->d_scale + b,
-                    h->d_disc + b, h->d_status + b, 2 * dl, 2 * dr, capk, h->cutoff, FIN_GATE};
+    mx[b] = MixItem{c, w, h->lcur(q), g[b].u, drv->d_fro2 + b, dl, dr};
+    jc[b] = JacItem{w, drv->d_fro2 + b, drv->d_rot + b, drv->d_sweeps + b, 2 * dl, 2 * dr, 0, 0, items};
+    fn[b] = FinItem{w, h->spare(q + 1), h->lspare(q + 1), drv->d_k + b, drv->d_scale + b,
+                    drv->d_disc + b, drv->d_status + b, 2 * dl, 2 * dr, capk, h->cutoff, FIN_GATE};
     // Eq. (Bl) with k read on the device: it is enqueued before the host
     // learns k; the result stays in the spare buffers until committed.
-    tr[b] = TruncItem{c, h->spare(q + 1), h->spare(q), h->d_scale + b, h->d_k + b, 2 * dl, dr, capk};
+    tr[b] = TruncItem{c, h->spare(q + 1), h->spare(q), drv->d_scale + b, drv->d_k + b, 2 * dl, dr, capk};
     max_rows = std::max(max_rows, 2 * dl);
     max_cols = std::max(max_cols, 2 * dr);
     max_dldr = std::max(max_dldr, dl * dr);
@@ -729,47 +773,64 @@ mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::v
   const size_t o_fn = place(fn.data(), sizeof(FinItem) * items);
   const size_t o_tr = place(tr.data(), sizeof(TruncItem) * items);
   const size_t o_jac = blob.size();
-  if ((st = ensure_desc(h, o_jac + 3 * sizeof(JacItem) * items + 512)) != MPS_OK) return st;
-  char* d = (char*)h->d_desc;
-  if ((st = upload(h, d, blob.data(), blob.size())) != MPS_OK) return st;
-  HIP_TRY(h, hipMemsetAsync(h->d_fro2, 0, sizeof(double) * items, h->stream));
-  HIP_TRY(h, hipMemsetAsync(h->d_rot, 0, sizeof(int) * items * h->max_sweeps, h->stream));
-  HIP_TRY(h, launch_theta((const ThetaItem*)(d + o_th), items, max_rows, max_cols, h->stream));
-  HIP_TRY(h, launch_mix((const MixItem*)(d + o_mx), items, max_dldr, h->stream));
+  if ((st = ensure_desc(drv, o_jac + 3 * sizeof(JacItem) * items + 512)) != MPS_OK) return st;
+  char* d = (char*)drv->d_desc;
+  if ((st = upload(drv, d, blob.data(), blob.size())) != MPS_OK) return st;
+  HIP_TRY(drv, hipMemsetAsync(drv->d_fro2, 0, sizeof(double) * items, drv->stream));
+  HIP_TRY(drv, hipMemsetAsync(drv->d_rot, 0, sizeof(int) * items * drv->max_sweeps, drv->stream));
+  HIP_TRY(drv, launch_theta((const ThetaItem*)(d + o_th), items, max_rows, max_cols, drv->stream));
+  HIP_TRY(drv, launch_mix((const MixItem*)(d + o_mx), items, max_dldr, drv->stream));
   std::vector<int> sweeps;
-  if ((st = run_jacobi(h, jc, o_jac, sweeps)) != MPS_OK) return st;
-  HIP_TRY(h, launch_finalize((const FinItem*)(d + o_fn), items, h->stream));
-  HIP_TRY(h, launch_trunc((const TruncItem*)(d + o_tr), items, max_rows, max_k, h->stream));
+  if ((st = run_jacobi(drv, jc, o_jac, sweeps)) != MPS_OK) return st;
+  HIP_TRY(drv, launch_finalize((const FinItem*)(d + o_fn), items, drv->stream));
+  HIP_TRY(drv, launch_trunc((const TruncItem*)(d + o_tr), items, max_rows, max_k, drv->stream));
   std::vector<int> k(items), status(items);
   std::vector<double> disc(items);
-  HIP_TRY(h, hipMemcpyAsync(k.data(), h->d_k, sizeof(int) * items, hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(status.data(), h->d_status, sizeof(int) * items,
-                            hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(disc.data(), h->d_disc, sizeof(double) * items,
-                            hipMemcpyDeviceToHost, h->stream));
-  if ((st = sync(h)) != MPS_OK) return st;
+  HIP_TRY(drv, hipMemcpyAsync(k.data(), drv->d_k, sizeof(int) * items, hipMemcpyDeviceToHost, drv->stream));
+  HIP_TRY(drv, hipMemcpyAsync(status.data(), drv->d_status, sizeof(int) * items, hipMemcpyDeviceToHost,
+                              drv->stream));
+  HIP_TRY(drv, hipMemcpyAsync(disc.data(), drv->d_disc, sizeof(double) * items, hipMemcpyDeviceToHost,
+                              drv->stream));
+  if ((st = sync(drv)) != MPS_OK) return st;
+  bool any_bad = false;
   for (int b = 0; b < items; ++b) {
-    if (sweeps[b] < 0)
-      return fail(MPS_ERR_NOCONV, "Jacobi SVD did not converge within " +
-                                      std::to_string(h->max_sweeps) + " sweeps (gate on qubit " +
-                                      std::to_string(qs[b]) + ")");
-    if (status[b] != 0)
-      return fail(MPS_ERR_NONFINITE, "non-finite or zero singular values (gate on qubit " +
-                                         std::to_string(qs[b]) + ")");
-    if (k[b] < 1 || k[b] > tr[b].k)
+    const std::string where = " (gate on qubit " + std::to_string(g[b].q) + ")";
+    if (sweeps[b] < 0 || sweeps[b] > g[b].h->max_sweeps) {
+      err[b] = MPS_ERR_NOCONV;
+      msg[b] = "Jacobi SVD did not converge within " + std::to_string(g[b].h->max_sweeps) + " sweeps" + where;
+    } else if (status[b] != 0) {
+      err[b] = MPS_ERR_NONFINITE;
+      msg[b] = "non-finite or zero singular values" + where;
+    } else if (k[b] < 1 || k[b] > tr[b].k) {
       return fail(MPS_ERR_STATE, "internal: kept rank out of range");
+    }
+    any_bad = any_bad || err[b] != MPS_OK;
+  }
+  if (any_bad && all_or_nothing) {
+    for (int b = 0; b < items; ++b)
+      if (err[b] != MPS_OK) return fail(err[b], msg[b]);
   }
   for (int b = 0; b < items; ++b) {
-    const int q = qs[b];
+    if (err[b] != MPS_OK) continue;
+    mps_state* h = g[b].h;
+    const int q = g[b].q;
     h->site_cur[q] ^= 1;
     h->site_cur[q + 1] ^= 1;
     h->lam_cur[q + 1] ^= 1;
     h->dims[q + 1] = k[b];
     h->discarded += disc[b];
+    h->canonical = false;
+    ++h->version;
   }
-  h->canonical = false;
-  ++h->version;
   return MPS_OK;
+}
+
+mps_status apply_2q_batch(mps_state* h, const std::vector<int>& qs, const std::vector<int>& gidx) {
+  std::vector<GateRef> g(qs.size());
+  for (size_t b = 0; b < qs.size(); ++b) g[b] = GateRef{h, qs[b], h->d_gates + (size_t)gidx[b] * 16};
+  std::vector<mps_status> err;
+  std::vector<std::string> msg;
+  return apply_2q_refs(h, g, true, err, msg);
 }
 
 // ----------------------------------------------------------------------------
@@ -1965,6 +2026,87 @@ mps_status mps_apply_gates(mps_handle h, int64_t ng, const int32_t* q0, const in
   return MPS_OK;
 }
 
+// mps_apply_gates_multi for lists with bonds above the fused limit: step k
+// applies gate k of every list that has one; its one-qubit gates first, then
+// its two-qubit gates -- on distinct handles, hence disjoint -- as one batch
+// of the multi-workgroup path (one batched contraction, Jacobi SVD and site
+// update), driven by the first handle on its stream.  A failed gate stops
+// only its own list.  Arguments were validated by the caller.
+mps_status apply_gates_multi_batched(int32_t n_handles, const mps_handle* hs, const int64_t* n_gates,
+                                     const int32_t* const* q0, const int32_t* const* q1,
+                                     const double* const* u, int64_t* n_done) {
+  const double t0 = now_ms();
+  mps_state* drv = hs[0];
+  mps_status st;
+  int64_t steps = 0;
+  for (int i = 0; i < n_handles; ++i) {
+    mps_state* h = hs[i];
+    const int64_t ng = n_gates[i];
+    steps = std::max(steps, ng);
+    if ((st = sync(h)) != MPS_OK) return st;
+    const size_t need = (size_t)std::max<int64_t>(ng, 1) * 16;
+    if (need > h->gates_cap) {
+      dfree(h, h->d_gates);
+      h->d_gates = nullptr;
+      h->gates_cap = 0;
+      if ((st = dalloc_t(h, &h->d_gates, need)) != MPS_OK) return st;
+      h->gates_cap = need;
+    }
+    if (ng > 0) HIP_TRY(h, hipMemcpy(h->d_gates, u[i], sizeof(double) * 32 * ng, hipMemcpyHostToDevice));
+  }
+  std::vector<char> alive(n_handles, 1);
+  std::vector<int64_t> done(n_handles, 0);
+  mps_status first = MPS_OK;
+  int first_handle = n_handles;
+  std::string first_msg;
+  std::vector<GateRef> refs;
+  std::vector<int> owner;
+  std::vector<mps_status> err;
+  std::vector<std::string> msg;
+  for (int64_t k = 0; k < steps; ++k) {
+    refs.clear();
+    owner.clear();
+    for (int i = 0; i < n_handles; ++i) {
+      if (!alive[i] || k >= n_gates[i]) continue;
+      mps_state* h = hs[i];
+      const int q = q0[i][k];
+      const double2* ug = h->d_gates + (size_t)k * 16;
+      if (q1[i][k] < 0) {
+        HIP_TRY(drv, launch_gate1q(h->cur(q), ug, h->dims[q] * h->dims[q + 1], drv->stream));
+        h->canonical = false;
+        ++h->version;
+        done[i] = k + 1;
+      } else {
+        refs.push_back(GateRef{h, q, ug});
+        owner.push_back(i);
+      }
+    }
+    if (refs.empty()) continue;
+    if ((st = apply_2q_refs(drv, refs, false, err, msg)) != MPS_OK) return st;
+    for (size_t b = 0; b < refs.size(); ++b) {
+      const int i = owner[b];
+      if (err[b] == MPS_OK) {
+        done[i] = k + 1;
+        continue;
+      }
+      alive[i] = 0;
+      if (i < first_handle) {
+        first_handle = i;
+        first = err[b];
+        first_msg = msg[b] + " (handle " + std::to_string(i) + ", gate " + std::to_string(k) + ")";
+      }
+    }
+  }
+  if ((st = sync(drv)) != MPS_OK) return st;
+  const double dt = now_ms() - t0;
+  for (int i = 0; i < n_handles; ++i) {
+    if (n_done) n_done[i] = done[i];
+    hs[i]->tm.gates_ms += dt;
+  }
+  if (first != MPS_OK) return fail(first, first_msg);
+  return MPS_OK;
+}
+
 mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const int64_t* n_gates,
                                  const int32_t* const* q0, const int32_t* const* q1,
                                  const double* const* u, void* stream, int64_t* n_done) {
@@ -1972,6 +2114,7 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const 
   if (n_handles == 0) return MPS_OK;
   if (!hs || !n_gates || !q0 || !q1 || !u) return fail(MPS_ERR_ARG, "NULL array");
   if (n_handles > 65535) return fail(MPS_ERR_ARG, "at most 65535 handles per call");
+  bool fused_mode = true;  // every two-qubit gate within the fused limit
   for (int i = 0; i < n_handles; ++i) {
     if (n_done) n_done[i] = 0;
     mps_status st = check_handle(hs[i]);
@@ -1988,13 +2131,13 @@ mps_status mps_apply_gates_multi(int32_t n_handles, const mps_handle* hs, const 
       if (a < 0 || a >= h->n) return fail(MPS_ERR_ARG, where + ": q0 out of range");
       if (b >= 0 && (b != a + 1 || b >= h->n))
         return fail(MPS_ERR_ARG, where + ": two-qubit gates must act on (q, q+1)");
-      if (b >= 0 && !fused_eligible(h, a))
-        return fail(MPS_ERR_ARG, where + ": bond capacity above the fused-gate limit (64)");
+      if (b >= 0 && !fused_eligible(h, a)) fused_mode = false;
       if (!finite_all(u[i] + 32 * g, b >= 0 ? 32 : 8))
         return fail(MPS_ERR_NONFINITE, where + ": non-finite matrix entry");
     }
   }
   const double t0 = now_ms();
+  if (!fused_mode) return apply_gates_multi_batched(n_handles, hs, n_gates, q0, q1, u, n_done);
   hipStream_t s = stream ? (hipStream_t)stream : hs[0]->stream;
   std::vector<FusedRun> runs(n_handles);
   int64_t steps = 0;

@@ -13,21 +13,25 @@ The loop (Server.run):
      device-memory budget (idle resident fragments are evicted, least recently
      used first, to make room); an admitted request resets its MPS to the
      Hartree-Fock product state;
-  2. advance every admitted request by one chunk of gates in one batched call
-     (mps_apply_gates_multi: one device launch per gate index, one workgroup
-     per request, so all dependent gate chains move together);
+  2. advance every admitted request by one chunk of gates, in two batched
+     calls (mps_apply_gates_multi) that run side by side: fragments whose
+     bonds are within the fused limit (capacity <= 64) take one device
+     launch per gate index, one workgroup per request; larger fragments take
+     batched steps, the step's gates of all of them in one multi-workgroup
+     SVD batch; either way all dependent gate chains move together;
   3. requests whose gates are done get their energy (the Pauli-sum
      expectation from the boundary environments, divided by <psi|psi>; no
-     canonicalisation sweep) between chunks;
+     canonicalisation sweep) between chunks; gradient-step requests (energy
+     and parameter-shift dE/dtheta of the fragment's UCCSD at the update's
+     angles) are also served between chunks;
   4. finished requests free their slot; arrivals are admitted between chunks.
 
 Energies run between gate chunks rather than beside them: the expectation
 path synchronises with the host many times, and streams
 beyond the device's few hardware queues share a queue in submission order, so
 each of those waits could otherwise stall behind a whole gate chunk.  Chunks
-are sized to a target duration so that arrivals wait at most about that long
-to join.  Fragments above the batched-gate limit (bond capacity > 64) are
-served whole (gates, then energy) between chunks.
+are sized (per group) to a target duration so that arrivals wait at most
+about that long to join.
 
 Latency of a request is arrival -> energy available; the report gives p50 and
 p99 next to the throughput.  The energy of a request does not depend on what
@@ -58,6 +62,9 @@ class Fragment:
     coeffs: np.ndarray
     updates: list                     # per update: (q0, q1, u_packed)
     est_bytes: int = 0                # device-memory estimate before first use
+    thetas: list | None = None        # per update: the UCCSD angles (gradient requests)
+    n_electrons: int = 0
+    window: int | None = None
 
     @property
     def n_terms(self) -> int:
@@ -66,10 +73,13 @@ class Fragment:
     @classmethod
     def from_dict(cls, d: dict) -> "Fragment":
         return cls(d["fid"], d["n_qubits"], d["max_bond"], d["cutoff"], d["bits"], d["codes"],
-                   d["coeffs"], d["updates"])
+                   d["coeffs"], d["updates"], thetas=d.get("thetas"), n_electrons=d.get("n_electrons", 0),
+                   window=d.get("window"))
 
     def batchable(self) -> bool:
-        """Every bond capacity <= 64: its gates can share the batched launches."""
+        """Every bond capacity <= 64: its gates run on the fused one-workgroup
+        path (else on batched multi-workgroup steps shared with the other
+        large fragments)."""
         return max(min(self.max_bond, 2 ** min(b, self.n_qubits - b))
                    for b in range(self.n_qubits + 1)) <= 64
 
@@ -85,6 +95,8 @@ class Request:
     finish: float = math.nan
     energy: float = math.nan
     error: str | None = None
+    kind: str = "energy"              # "energy" | "gradient" (energy and dE/dtheta)
+    gradient: np.ndarray | None = None
 
     @property
     def latency(self) -> float:
@@ -120,6 +132,7 @@ class GpuBackend:
         self.prec = prec
         self.stream = torch.cuda.Stream()
         self.plans: dict[int, object] = {}
+        self.grads: dict[int, object] = {}
 
     def _plan(self, frag: Fragment):
         if frag.fid not in self.plans:
@@ -146,9 +159,19 @@ class GpuBackend:
     def expect(self, handle, frag: Fragment) -> float:
         return handle.expect(self._plan(frag), self.prec)
 
-    def apply_all(self, handle, frag: Fragment, update: int):
-        q0, q1, u = frag.updates[update]
-        handle.apply_gates(q0, q1, u)
+    def gradient(self, frag: Fragment, update: int):
+        """Energy and parameter-shift gradient of the fragment's UCCSD at the
+        update's angles (f1); the gradient engine and its handles are kept
+        per fragment."""
+        from .gradients import UccsdGradient
+        if frag.thetas is None:
+            raise ValueError(f"fragment {frag.fid} carries no UCCSD angles")
+        g = self.grads.get(frag.fid)
+        if g is None:
+            g = UccsdGradient(frag.n_qubits, frag.n_electrons, self._plan(frag), frag.max_bond,
+                              frag.cutoff, bits=frag.bits, window=frag.window, prec=self.prec)
+            self.grads[frag.fid] = g
+        return g.energy_and_gradient(frag.thetas[update])
 
     def device_bytes(self, handle) -> int:
         return int(handle.device_bytes())
@@ -157,7 +180,9 @@ class GpuBackend:
         handle.close()
 
     def shutdown(self):
-        pass
+        for g in self.grads.values():
+            g.close()
+        self.grads.clear()
 
 
 # --------------------------------------------------------------------------
@@ -266,13 +291,13 @@ class Server:
         upcoming = list(reqs)
         active: list[_Active] = []                     # gate chains in progress
         ready: list[_Active] = []                      # gates done, energy pending
-        whole: list[_Active] = []                      # served whole (above the batched limit)
+        grads: list[_Active] = []                      # gradient requests (served between chunks)
         done: list[Request] = []
         t0 = self.clock()
         active_samples = []
         max_seen = 0
         strings = 0
-        steps = self.chunk
+        steps = {True: self.chunk, False: self.chunk}  # chunk length per group (fused / batched)
 
         def finish(a: _Active, energy=None, error=None):
             nonlocal strings
@@ -295,7 +320,7 @@ class Server:
                 waiting.append(upcoming.pop(0))
             # 1. admission (arrival order; a request waits for its fragment's
             #    previous update and for a slot and memory)
-            in_flight = len(active) + len(ready) + len(whole)
+            in_flight = len(active) + len(ready) + len(grads)
             idle_before = in_flight == 0
             still = []
             for r in waiting:
@@ -315,7 +340,7 @@ class Server:
                 self.backend.reset(h, frag)
                 r.admitted = self.clock() - t0
                 self.busy.add(r.fid)
-                (active if frag.batchable() else whole).append(_Active(r, frag, h))
+                (grads if r.kind == "gradient" else active).append(_Active(r, frag, h))
                 in_flight += 1
             # nothing was in flight and nothing could be admitted: no later
             # completion can free memory, so the budget is too small
@@ -323,61 +348,82 @@ class Server:
                 r.update == next_update[r.fid] and r.fid not in self.busy for r in waiting[:1])
             waiting = still
             max_seen = max(max_seen, in_flight)
-            # 2. energies of requests whose gates are done; whole requests
+            # 2. energies of requests whose gates are done; gradient requests
             for a in ready:
                 try:
                     finish(a, self.backend.expect(a.handle, a.frag))
                 except Exception as err:
                     finish(a, error=str(err))
             ready = []
-            for a in whole:
+            for a in grads:
                 try:
-                    self.backend.apply_all(a.handle, a.frag, a.req.update)
+                    e, g = self.backend.gradient(a.frag, a.req.update)
+                    a.req.gradient = np.asarray(g)
                     a.req.gates_done = self.clock() - t0
-                    finish(a, self.backend.expect(a.handle, a.frag))
+                    finish(a, e)
                 except Exception as err:
                     finish(a, error=str(err))
-            whole = []
-            # 3. one gate chunk for every admitted request
+            grads = []
+            # 3. one gate chunk for every admitted request: fragments within the
+            #    fused limit advance together on one-workgroup launches, larger
+            #    ones together on batched multi-workgroup steps; the two groups'
+            #    calls run side by side (the library releases the interpreter)
             if active:
-                items = []
+                groups = {}
                 for a in active:
-                    q0, q1, u = a.frag.updates[a.req.update]
-                    c1 = min(len(q0), a.cursor + steps)
-                    items.append((a.handle, q0[a.cursor:c1], q1[a.cursor:c1], u[a.cursor:c1]))
+                    groups.setdefault(a.frag.batchable(), []).append(a)
                 active_samples.append(len(active))
-                tc = self.clock()
-                failed = None
-                try:
-                    applied = self.backend.apply_chunk(items)
-                except Exception as err:  # a failed gate: only its request fails
-                    applied = getattr(err, "n_done", None)
-                    failed = err
-                    if applied is None:
-                        raise
-                dt = self.clock() - tc
-                self.chunks += 1
-                longest = max(len(it[1]) for it in items)
-                if longest > 0 and dt > 0:  # size the next chunk to the target duration
-                    steps = int(min(self.max_chunk, max(16, self.chunk_s * longest / dt)))
+
+                def run_group(small, members):
+                    items = []
+                    for a in members:
+                        q0, q1, u = a.frag.updates[a.req.update]
+                        c1 = min(len(q0), a.cursor + steps[small])
+                        items.append((a.handle, q0[a.cursor:c1], q1[a.cursor:c1], u[a.cursor:c1]))
+                    tc = self.clock()
+                    failed = None
+                    try:
+                        applied = self.backend.apply_chunk(items)
+                    except Exception as err:  # a failed gate: only its request fails
+                        applied = getattr(err, "n_done", None)
+                        failed = err
+                        if applied is None:
+                            raise
+                    return items, applied, failed, self.clock() - tc
+
+                if len(groups) > 1:
+                    from concurrent.futures import ThreadPoolExecutor
+                    with ThreadPoolExecutor(max_workers=2) as pool:
+                        futs = {k: pool.submit(run_group, k, v) for k, v in groups.items()}
+                        results = {k: f.result() for k, f in futs.items()}
+                else:
+                    results = {k: run_group(k, v) for k, v in groups.items()}
                 keep = []
-                for a, it, k in zip(active, items, applied):
-                    n_slice = len(it[1])
-                    if k < n_slice:  # this request's gate failed
-                        finish(a, error=str(failed))
-                        continue
-                    a.cursor += n_slice
-                    if a.cursor >= len(a.frag.updates[a.req.update][0]):
-                        a.req.gates_done = self.clock() - t0
-                        ready.append(a)
-                    else:
-                        keep.append(a)
-                if self.log:
-                    self.log(f"chunk {self.chunks}: {len(items)} chains x {longest} gates in "
-                             f"{dt:.2f} s; {len(done)}/{len(reqs)} done")
+                for small, members in groups.items():
+                    items, applied, failed, dt = results[small]
+                    self.chunks += 1
+                    longest = max(len(it[1]) for it in items)
+                    if longest > 0 and dt > 0:  # size the group's next chunk to the target duration,
+                        # growing at most 2x a chunk (early gates, on small bonds, are far cheaper)
+                        want = min(self.chunk_s * longest / dt, 2 * longest)
+                        steps[small] = int(min(self.max_chunk, max(16, want)))
+                    for a, it, k in zip(members, items, applied):
+                        n_slice = len(it[1])
+                        if k < n_slice:  # this request's gate failed
+                            finish(a, error=str(failed))
+                            continue
+                        a.cursor += n_slice
+                        if a.cursor >= len(a.frag.updates[a.req.update][0]):
+                            a.req.gates_done = self.clock() - t0
+                            ready.append(a)
+                        else:
+                            keep.append(a)
+                    if self.log:
+                        self.log(f"chunk {self.chunks} ({'fused' if small else 'batched'}): {len(items)} "
+                                 f"chains x {longest} gates in {dt:.2f} s; {len(done)}/{len(reqs)} done")
                 active = keep
             # 4. idle: wait for the next arrival
-            if not active and not ready:
+            if not active and not ready and not grads:
                 if stuck:
                     r = waiting[0]
                     raise RuntimeError(f"request {r.rid} (fragment {r.fid}) cannot be admitted: "

@@ -71,14 +71,49 @@ def test_apply_gates_multi_matches_single(gpu_lib):
         assert np.max(np.abs(pb - ref)) < 1e-10
 
 
-def test_apply_gates_multi_rejects_large_bonds(gpu_lib):
+def test_apply_gates_multi_batches_large_bonds(gpu_lib):
+    """Lists with bonds above the fused limit advance as batched steps across
+    MPSs (one SVD batch per step): the same states as mps_apply_gates on each
+    MPS alone (rounding), the oracle without cap truncation, and a failed
+    list stops alone."""
     from paper_2303_03681_amd import binding
-    m = binding.Mps(16, 128, 1e-14)
-    q0, q1, u = pack_gates([Gate(7, 8, np.eye(4, dtype=complex))])
+    shapes = [(16, 128, 2), (14, 128, 2), (12, 64, 3), (10, 256, 2)]
+    lists, singles, multis, oracles = [], [], [], []
+    for i, (n, D, sw) in enumerate(shapes):
+        gates = _ladder(n, sw, 700 + i)
+        lists.append(pack_gates(gates))
+        bits = hf_bits(n, n // 2)
+        a = binding.Mps(n, D, 1e-14, bits=bits)
+        a.apply_gates(*lists[-1])
+        singles.append(a)
+        multis.append(binding.Mps(n, D, 1e-14, bits=bits))
+        o = MpsOracle(n, D, 1e-14, bits)
+        o.apply_gates(gates)
+        oracles.append(o)
+    _say("apply_gates_multi, batched steps over 4 MPSs with bonds up to 128")
+    done = binding.apply_gates_multi(multis, lists)
+    assert list(done) == [len(l[0]) for l in lists]
+    r = np.random.default_rng(1)
+    for (n, D, _), a, b, o in zip(shapes, singles, multis, oracles):
+        assert list(b.bond_dims()) == list(a.bond_dims()) == o.bond_dims()
+        assert abs(b.discarded_weight() - a.discarded_weight()) < 1e-13
+        codes = r.integers(0, 4, size=(100, n)).astype(np.uint8)
+        plan = binding.PauliSum(codes, r.normal(size=100))
+        _, pa = a.expect(plan, "c128", per_term=True)
+        _, pb = b.expect(plan, "c128", per_term=True)
+        o.canonicalize()
+        ref = o.expect_terms(codes).real
+        d_ab, d_ref = float(np.max(np.abs(pa - pb))), float(np.max(np.abs(pb - ref)))
+        _say(f"  {n} q D={D}: max |d<P>| vs single {d_ab:.2e}, vs oracle {d_ref:.2e}")
+        assert d_ab < 1e-10 and d_ref < 1e-10
+    # a list whose SVD cannot converge (sweep limit 1) stops alone
+    bad = binding.Mps(16, 128, 1e-14, bits=hf_bits(16, 8), max_jacobi_sweeps=1)
+    good = binding.Mps(16, 128, 1e-14, bits=hf_bits(16, 8))
     with pytest.raises(binding.MpsError) as ex:
-        binding.apply_gates_multi([m], [(q0, q1, u)])
-    assert ex.value.name == "MPS_ERR_ARG"
-    assert list(m.bond_dims()) == [1] * 17
+        binding.apply_gates_multi([good, bad], [lists[0], lists[0]])
+    assert ex.value.name == "MPS_ERR_NOCONV"
+    assert ex.value.n_done[0] == len(lists[0][0]) and ex.value.n_done[1] < len(lists[0][0])
+    assert list(good.bond_dims()) == list(singles[0].bond_dims())
 
 
 def _serve(frags, reqs, **kw):
@@ -128,6 +163,46 @@ def test_serving_alone_vs_mix_and_oracle(gpu_lib):
     o.canonicalize()
     e_ref = math.fsum(f.coeffs * o.expect_terms(f.codes).real)
     assert abs(e_mix[(k, 1)] - e_ref) < 1e-9
+
+
+def test_serving_gradient_request_and_large_fragments(gpu_lib):
+    """A gradient-step request in the mix returns the energy and the
+    parameter-shift gradient of its fragment's UCCSD at the update's angles,
+    equal to the gradient engine run directly; a fragment above the fused
+    limit (D = 128 at 14 qubits: bond capacity 128, never cut at the cap) is
+    served on batched steps beside the small ones and gives the single-MPS
+    energy.  (With cuts at the cap, near-degenerate singular values would let
+    the two paths' different rotation orders take different valid
+    truncations.)"""
+    from paper_2303_03681_amd import binding
+    from paper_2303_03681_amd.gradients import UccsdGradient
+    from paper_2303_03681_amd.serving import Fragment, Request
+    raw = build_serving_fragments(3, 2, qubits=(8,), bonds=(16,), max_strings=300)
+    raw += build_serving_fragments(1, 1, qubits=(14,), bonds=(128,), max_strings=300)
+    raw[3]["fid"] = 3
+    frags = [Fragment.from_dict(d) for d in raw]
+    assert not frags[3].batchable()
+    reqs = [Request(0, 0, 0, 0.0), Request(1, 1, 0, 0.0, kind="gradient"), Request(2, 2, 0, 0.0),
+            Request(3, 3, 0, 0.0), Request(4, 0, 1, 0.01), Request(5, 1, 1, 0.01, kind="gradient")]
+    _say("serving mix with gradient requests and a D = 128 fragment")
+    rep, _ = _serve(frags, reqs, max_active=8, chunk=64)
+    assert rep.completed == len(reqs)
+    by = {r.rid: r for r in rep.requests}
+    f = frags[1]
+    g = UccsdGradient(f.n_qubits, f.n_electrons, binding.PauliSum(f.codes, f.coeffs), f.max_bond,
+                      f.cutoff, bits=f.bits, window=f.window, prec="c128")
+    for rid, upd in ((1, 0), (5, 1)):
+        e, grad = g.energy_and_gradient(f.thetas[upd])
+        _say(f"  gradient request {rid}: |dE| {abs(e - by[rid].energy):.2e}, "
+             f"max |d grad| {np.max(np.abs(grad - by[rid].gradient)):.2e}, |grad| {np.linalg.norm(grad):.3e}")
+        assert abs(e - by[rid].energy) <= 1e-12 and np.max(np.abs(grad - by[rid].gradient)) <= 1e-12
+    g.close()
+    big = frags[3]
+    m = binding.Mps(big.n_qubits, big.max_bond, big.cutoff, bits=big.bits)
+    m.apply_gates(*big.updates[0])
+    e_api = m.expect(binding.PauliSum(big.codes, big.coeffs), "c128")
+    _say(f"  D = 128 fragment: |E_mix - E_single| {abs(e_api - by[3].energy):.2e}")
+    assert abs(e_api - by[3].energy) < 1e-9
 
 
 def test_serving_budget_evicts_and_keeps_results(gpu_lib):

@@ -160,7 +160,7 @@ def test_fragment_batchable_limit_and_estimate():
     assert estimate_bytes(24, 64, 1000) > estimate_bytes(24, 32, 1000) > 0
 
 
-def test_fragments_above_batched_limit_are_served_whole():
+def test_fragments_above_fused_limit_advance_in_their_own_group():
     frags = _frags(2, gates_per_update=(400,), n_updates=1, qubits=16, bond=128)
     frags += _frags(1, gates_per_update=(900,), n_updates=1)
     frags[2].fid = 2
@@ -168,6 +168,29 @@ def test_fragments_above_batched_limit_are_served_whole():
     reqs = [Request(i, i, 0, 0.0) for i in range(3)]
     rep = Server(frags, be, max_active=8, chunk=128, max_chunk=128).run(reqs)
     assert rep.completed == 3
-    assert all(m == (2,) for m in be.chunk_members)  # only the batchable one is chunked
+    # every chunk call holds only fused-limit fragments (2) or only larger ones (0, 1)
+    assert set(be.chunk_members) <= {(2,), (0, 1), (0,), (1,)}
+    assert (2,) in be.chunk_members and (0, 1) in be.chunk_members
     for r in rep.requests:
         assert r.energy == pytest.approx(r.fid + 0.001 * frags[r.fid].updates[0][0].size)
+
+
+def test_gradient_requests_served_between_chunks():
+    frags = _frags(2, gates_per_update=(300,), n_updates=2)
+    for f in frags:
+        f.thetas = [np.full(3, 0.1 * (u + 1)) for u in range(2)]
+
+    class GradBackend(FakeBackend):
+        def gradient(self, frag, update):
+            return float(frag.fid) + 0.5, np.asarray(frag.thetas[update]) * 2.0
+
+    be = GradBackend()
+    reqs = [Request(0, 0, 0, 0.0), Request(1, 1, 0, 0.0, kind="gradient"),
+            Request(2, 0, 1, 0.0), Request(3, 1, 1, 0.0, kind="gradient")]
+    rep = Server(frags, be, max_active=8, chunk=64).run(reqs)
+    assert rep.completed == 4
+    by = {r.rid: r for r in rep.requests}
+    assert by[1].energy == 1.5 and np.allclose(by[1].gradient, 0.2)
+    assert by[3].energy == 1.5 and np.allclose(by[3].gradient, 0.4)
+    assert by[0].gradient is None and by[0].energy == pytest.approx(0.001 * 300)
+    assert all(m == (0,) for m in be.chunk_members)  # gradient requests take no gate chunks

@@ -111,5 +111,6 @@ def build_serving_fragments(n_fragments: int, n_updates: int,
         updates = [pack_gates(fuse_gates(uccsd_gates(n, ne, th, window=window), n)) for th in thetas]
         out.append({"fid": fid, "n_qubits": n, "max_bond": D, "cutoff": cutoff,
                     "bits": hf_bits(n, ne), "codes": psum.codes, "coeffs": psum.coeffs,
-                    "updates": updates, "full_terms": full.n_terms})
+                    "updates": updates, "full_terms": full.n_terms,
+                    "thetas": [np.array(t) for t in thetas], "n_electrons": ne, "window": window})
     return out
