@@ -1,8 +1,11 @@
-"""GPU, opt-in (MPS_C5=1; about 5 minutes): the 100-qubit configuration --
-brickwork 40 layers truncated to D = 512, 2^20 strings sampled from the JW
-expansion -- with the strings in memory-bounded chunks, c64 against c128,
-and a few per-string c128 values against the oracle's full contraction of the
-same (exported) state."""
+"""GPU: the 100-qubit configuration -- brickwork truncated to D = 512,
+strings sampled from the JW expansion of 50 orbitals -- with the strings in
+memory-bounded chunks summed on the device, c64 against c128, and per-string
+c128 values against the oracle's full contraction of the same (exported)
+state.  The default run takes 12 layers (the centre bonds saturate at 512
+from layer 9, so the last sub-layers carry 1024-row SVDs) and 4,096
+strings in two chunks; the whole configuration (40 layers, 2^20 strings, 16
+chunks; about 5 minutes) is opt-in with MPS_C5=1."""
 
 import json
 import os
@@ -13,15 +16,16 @@ import pytest
 
 from workloads import build_config, pack_gates
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("MPS_C5") != "1",
-                                 reason="100 qubits at D = 512 runs for minutes; set MPS_C5=1")]
+pytestmark = pytest.mark.gpu
+full_run = pytest.mark.skipif(os.environ.get("MPS_C5") != "1",
+                              reason="100 qubits at D = 512 runs for minutes; set MPS_C5=1")
 
 
 def _say(msg):
     print(msg, flush=True)
 
 
+@full_run
 def test_c5_brickwork_100q_d512(gpu_lib):
     from oracle import MpsOracle
     from paper_2303_03681_amd import binding
@@ -71,3 +75,47 @@ def test_c5_brickwork_100q_d512(gpu_lib):
             json.dump(res, f, indent=1)
     assert max(diffs) < 1e-10
     assert res["abs_dE_c64_vs_c128"] < 1e-6
+
+
+def test_c5_shape_default(gpu_lib):
+    from oracle import MpsOracle
+    from paper_2303_03681_amd import binding
+    from paper_2303_03681_amd.chunked import ChunkedPauliSum
+    t0 = time.time()
+    w = build_config(5, layers=12, n_strings=4096)
+    _say(f"C5 shape: 100 q, 12 layers, D = 512, {w.psum.n_terms} strings of {w.full_terms} "
+         f"(built in {time.time() - t0:.0f} s)")
+    q0, q1, u = pack_gates(w.gates)
+    m = binding.Mps(w.n_qubits, 512, w.spec.cutoff, bits=w.bits)
+    m.set_timing(True)
+    t1 = time.time()
+    assert m.apply_gates(q0, q1, u) == len(q0)
+    tm = m.timing()
+    dims = m.bond_dims()
+    _say(f"  gates {time.time() - t1:.1f} s, max bond {dims.max()}, wide-row SVDs {tm['jacobi_wide_items']}, "
+         f"discarded {m.discarded_weight():.4f}")
+    assert dims.max() == 512 and tm["jacobi_wide_items"] > 0
+    # random 100-qubit strings share few prefixes: one plan of all 4096 would
+    # hold ~3e5 MB of complex128 environments, so the strings go in chunks
+    # (2 and 4 of them; the per-chunk energy pairs are added on the device)
+    ch2 = ChunkedPauliSum(w.psum.codes, w.psum.coeffs, 2048)
+    ch4 = ChunkedPauliSum(w.psum.codes, w.psum.coeffs, 1024)
+    assert len(ch2.plans) == 2 and len(ch4.plans) == 4
+    e128, p128 = ch2.expect(m, "c128", per_term=True)
+    e4, p4 = ch4.expect(m, "c128", per_term=True)
+    e64 = ch4.expect(m, "c64")
+    _say(f"  c128 in 2 chunks {e128:.15f}, in 4 chunks {e4:.15f}; |c64 - c128| {abs(e64 - e128):.2e}")
+    assert np.max(np.abs(p128 - p4)) < 1e-12 and abs(e128 - e4) < 1e-12
+    assert abs(e64 - e128) < 1e-6
+    o = MpsOracle(w.n_qubits, 512, w.spec.cutoff, w.bits)
+    o.B = [m.export_site(q)[0] for q in range(w.n_qubits)]
+    worst = 0.0
+    for k in np.argsort(-np.abs(p128))[:3]:
+        t2 = time.time()
+        ref = o.expect_pauli_full(w.psum.codes[k]).real
+        worst = max(worst, abs(ref - p128[k]))
+        _say(f"  oracle string {k}: {ref:.3e}, |d| {abs(ref - p128[k]):.1e} ({time.time() - t2:.0f} s)")
+    assert worst < 1e-10
+    m.close()
+    ch2.close()
+    ch4.close()
