@@ -285,21 +285,34 @@ struct RegVec {
   double2 v[E];
 };
 
+// Row pointers of the Jacobi work matrices are global memory: typed so, the
+// loads and stores are global (not flat) instructions with immediate offsets.
+typedef double __attribute__((ext_vector_type(2))) dvec2;
+typedef __attribute__((address_space(1))) dvec2 gdvec2;
+
+// Every lane loads (unconditionally, from inside the row: indices past the
+// row end are clamped to its last element; src is always a row of the
+// matrix) and zeroes what lies outside the row or belongs to a padding row,
+// so the loads need no branches.
 template <int E>
 __device__ __forceinline__ void rv_load(RegVec<E>& r, const double2* src, int valid, int m, int lane) {
+  const gdvec2* g = (const gdvec2*)src;
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int e = lane + 64 * k;
-    r.v[k] = (valid && e < m) ? src[e] : make_double2(0.0, 0.0);
+    const dvec2 v = g[e < m ? e : m - 1];
+    const bool keep = valid && e < m;
+    r.v[k] = make_double2(keep ? v.x : 0.0, keep ? v.y : 0.0);
   }
 }
 
 template <int E>
 __device__ __forceinline__ void rv_store(const RegVec<E>& r, double2* dst, int m, int lane) {
+  gdvec2* g = (gdvec2*)dst;
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int e = lane + 64 * k;
-    if (e < m) dst[e] = r.v[k];
+    if (e < m) g[e] = dvec2{r.v[k].x, r.v[k].y};
   }
 }
 
