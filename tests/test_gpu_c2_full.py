@@ -1,0 +1,141 @@
+"""GPU, opt-in: the 24-qubit workload with the full UCCSD circuit (Eq. ucc;
+12 orbitals, 12 electrons, 420,077 two-qubit gates after folding, a strictly
+sequential chain) at the workload's D = 64, cutoff 1e-10.
+
+At about 2.7 ms per gate the circuit needs about 19 minutes of gates, more
+than one bounded run, so the test is resumable: it applies gates for at most
+MPS_C2_FULL_SECONDS (default 540) and then writes the state (every site
+tensor and left lambda, exported exactly in FP64), the next gate index, the
+discarded weight so far and the check statistics to MPS_C2_FULL_OUT; a later
+run given that directory as MPS_C2_FULL_IN imports the sites and continues.
+Export and import copy the FP64 site tensors bit for bit, so the pieces run
+the same gates on the same state as one uninterrupted run would.
+
+Every 2000th two-qubit gate is checked as in the windowed D = 64 case: the two
+sites and the left lambda are exported before the gate, the oracle applies the
+same gate (Eqs. C, C~, svd, Bl with its LAPACK SVD), and the new bond
+dimension, the kept singular values (1e-12 of the largest) and the gate's
+discarded weight (1e-12) must match.  When the last gate has run, the energy
+over the 29,737 JW strings is evaluated in complex128 and complex64 and the
+two must agree to 1e-6; the result is written to MPS_C2_FULL_OUT/result.json.
+"""
+
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from tests.gate_check import check_gate
+from workloads import build_config, pack_gates
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not os.environ.get("MPS_C2_FULL_OUT"),
+                                 reason="full 24-qubit UCCSD (~19 min of gates, resumable): "
+                                        "set MPS_C2_FULL_OUT (and MPS_C2_FULL_IN to resume)")]
+
+CHECK_EVERY = 2000
+D, CUTOFF = 64, 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _load(path, n):
+    z = np.load(os.path.join(path, "state.npz"))
+    meta = json.loads(str(z["meta"]))
+    sites = [(z[f"b{q}"], z[f"l{q}"]) for q in range(n)]
+    return meta, sites
+
+
+def _save(path, m, n, meta):
+    os.makedirs(path, exist_ok=True)
+    arrs = {}
+    for q in range(n):
+        b, lam = m.export_site(q)
+        arrs[f"b{q}"] = b
+        arrs[f"l{q}"] = lam
+    np.savez(os.path.join(path, "state.npz"), meta=json.dumps(meta), **arrs)
+
+
+def test_c2_full_uccsd_d64(gpu_lib):
+    from paper_2303_03681_amd import binding
+    budget = float(os.environ.get("MPS_C2_FULL_SECONDS", "540"))
+    out_dir = os.environ["MPS_C2_FULL_OUT"]
+    in_dir = os.environ.get("MPS_C2_FULL_IN")
+    t0 = time.time()
+    w = build_config(2)
+    assert w.spec.max_bond == D and w.spec.cutoff == CUTOFF
+    q0, q1, u = pack_gates(w.gates)
+    n = w.n_qubits
+    two = np.nonzero(q1 >= 0)[0]
+    _say(f"C2 full UCCSD: {n} q, {len(q0)} gates ({two.size} two-qubit), D={D}; built in "
+         f"{time.time() - t0:.0f} s")
+    m = binding.Mps(n, D, CUTOFF, bits=w.bits)
+    meta = {"next": 0, "disc_before": 0.0, "checks": 0, "cap_cuts": 0, "min_gap": None,
+            "max_dlam": 0.0, "max_dw": 0.0, "gate_seconds": 0.0, "pieces": 0}
+    if in_dir:
+        meta, sites = _load(in_dir, n)
+        for q, (b, lam) in enumerate(sites):
+            m.import_site(q, b, lam)
+        _say(f"  resumed at gate {meta['next']} (discarded so far {meta['disc_before']:.6e})")
+    start = meta["next"]
+    checks = two[(np.arange(two.size) % CHECK_EVERY == 0)]
+    checks = checks[checks >= start]
+    tg = time.time()
+    done = start
+    last_say = tg
+    for g in list(checks) + [len(q0)]:
+        g = int(g)
+        if time.time() - tg > budget:
+            break
+        # gates up to g in slices, so the time budget is kept
+        while done < g and time.time() - tg <= budget:
+            e = min(g, done + 20000)
+            assert m.apply_gates(q0[done:e], q1[done:e], u[done:e]) == e - done
+            done = e
+        if done < g or g == len(q0):
+            break
+        dl, ddw, k, s = check_gate(m, g, q0, q1, u, D, CUTOFF)
+        done = g + 1
+        meta["max_dlam"] = max(meta["max_dlam"], dl)
+        meta["max_dw"] = max(meta["max_dw"], ddw)
+        assert dl <= 1e-12 and ddw <= 1e-12, (g, dl, ddw)
+        meta["checks"] += 1
+        if k == D and s.size > D and s[D] > CUTOFF * np.linalg.norm(s):
+            meta["cap_cuts"] += 1
+            gap = float((s[D - 1] - s[D]) / s[0])
+            meta["min_gap"] = gap if meta["min_gap"] is None else min(meta["min_gap"], gap)
+        if time.time() - last_say > 30:
+            last_say = time.time()
+            rate = (done - start) / (last_say - tg)
+            _say(f"  gate {done} of {len(q0)} ({rate:.0f} gates/s), checks {meta['checks']}, "
+                 f"max bond {m.bond_dims().max()}, max |d lambda| {meta['max_dlam']:.1e}")
+    meta["gate_seconds"] += time.time() - tg
+    meta["pieces"] += 1
+    disc = meta["disc_before"] + m.discarded_weight()
+    _say(f"  stopped at gate {done} of {len(q0)} after {time.time() - tg:.0f} s; checks {meta['checks']} "
+         f"(cap cuts {meta['cap_cuts']}, smallest relative gap {meta['min_gap']}), "
+         f"max |d lambda| {meta['max_dlam']:.2e}, max |d w| {meta['max_dw']:.2e}, discarded {disc:.6e}")
+    meta["next"] = done
+    meta["disc_before"] = disc
+    if done < len(q0):
+        _save(out_dir, m, n, meta)
+        m.close()
+        return
+    plan = binding.PauliSum(w.psum.codes, w.psum.coeffs)
+    e128 = m.expect(plan, "c128")
+    e64 = m.expect(plan, "c64")
+    res = dict(meta, energy_c128=e128, energy_c64=e64, abs_dE_c64=abs(e64 - e128),
+               n_gates=len(q0), n_two_qubit=int(two.size), n_terms=w.psum.n_terms,
+               bond_dims=[int(x) for x in m.bond_dims()])
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "result.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    _say(f"  E c128 {e128:.12f}, c64 {e64:.12f}, |dE| {abs(e64 - e128):.2e}; "
+         f"{meta['gate_seconds']:.0f} s of gates in {meta['pieces']} pieces")
+    assert abs(e64 - e128) < 1e-6
+    m.close()
+    plan.close()
