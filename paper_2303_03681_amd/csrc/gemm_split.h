@@ -17,7 +17,8 @@
 // The problem functors are those of cgemm_kernel (gemm_core.h) with T = float;
 // the tile loop, XCD remap and operand handles follow cgemm_kernel, with the
 // split done when a staged FP32 tile is written to LDS (8 consecutive k per
-// thread, each 16-bit plane stored as one 16-byte vector).
+// thread, each 16-bit plane stored as one 16-byte vector), into the second of
+// two LDS buffers while the matrix cores take the first.
 //
 // MFMA 16x16x32 operand layout (wave64), lane l, j = 0..7:
 //   A fragment A[l % 16][8 (l / 16) + j], B fragment B[8 (l / 16) + j][l % 16],
@@ -75,9 +76,11 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
 
-  // [0] leading real, [1] leading imaginary, [2] trailing real, [3] trailing imaginary
-  __shared__ __attribute__((aligned(16))) L As[4][BM][KP];
-  __shared__ __attribute__((aligned(16))) L Bs[4][BN][KP];
+  // Two buffers; in each, [0] leading real, [1] leading imaginary, [2]
+  // trailing real, [3] trailing imaginary.  While the matrix cores work on one
+  // K-chunk, the next chunk is split and stored into the other buffer.
+  __shared__ __attribute__((aligned(16))) L As[2][4][BM][KP];
+  __shared__ __attribute__((aligned(16))) L Bs[2][4][BN][KP];
 
   const int logical = xcd_remap(blockIdx.x, g8);
   if (logical >= total) return;
@@ -134,18 +137,18 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
       il[j] = (L)((v[j].y - (float)hi0) * Tr::S);
     }
   };
-  auto store_tiles = [&]() {
+  auto store_tiles = [&](int buf) {
     V8 p0, p1, p2, p3;
     split8(ra, p0, p1, p2, p3);
-    *(V8*)&As[0][a_i][a_k] = p0;
-    *(V8*)&As[1][a_i][a_k] = p1;
-    *(V8*)&As[2][a_i][a_k] = p2;
-    *(V8*)&As[3][a_i][a_k] = p3;
+    *(V8*)&As[buf][0][a_i][a_k] = p0;
+    *(V8*)&As[buf][1][a_i][a_k] = p1;
+    *(V8*)&As[buf][2][a_i][a_k] = p2;
+    *(V8*)&As[buf][3][a_i][a_k] = p3;
     split8(rb, p0, p1, p2, p3);
-    *(V8*)&Bs[0][b_j][b_k] = p0;
-    *(V8*)&Bs[1][b_j][b_k] = p1;
-    *(V8*)&Bs[2][b_j][b_k] = p2;
-    *(V8*)&Bs[3][b_j][b_k] = p3;
+    *(V8*)&Bs[buf][0][b_j][b_k] = p0;
+    *(V8*)&Bs[buf][1][b_j][b_k] = p1;
+    *(V8*)&Bs[buf][2][b_j][b_k] = p2;
+    *(V8*)&Bs[buf][3][b_j][b_k] = p3;
   };
 
   f4_t hr[FM][FN], hi[FM][FN], xr[FM][FN], xi[FM][FN];  // leading / cross accumulators
@@ -157,20 +160,21 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
       for (int v = 0; v < 4; ++v) hr[i][j][v] = hi[i][j][v] = xr[i][j][v] = xi[i][j][v] = 0.f;
 
   load_tiles(0);
+  store_tiles(0);
+  __syncthreads();
+  int cur = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    store_tiles();
-    __syncthreads();
-    if (k0 + BK < K) load_tiles(k0 + BK);
+    const bool more = k0 + BK < K;
+    if (more) load_tiles(k0 + BK);
     V8 a[FM][4], b[FN][4];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a[i][c] = *(const V8*)&As[c][wm + i * 16 + lr][frag32_k(lane, 0)];
+      for (int c = 0; c < 4; ++c) a[i][c] = *(const V8*)&As[cur][c][wm + i * 16 + lr][frag32_k(lane, 0)];
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) b[j][c] = *(const V8*)&Bs[c][wn + j * 16 + lr][frag32_k(lane, 0)];
+      for (int c = 0; c < 4; ++c) b[j][c] = *(const V8*)&Bs[cur][c][wn + j * 16 + lr][frag32_k(lane, 0)];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       const V8 nih = neg8(a[i][1]), nil = neg8(a[i][3]);
@@ -191,6 +195,10 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
         xi[i][j] = Tr::mfma(a[i][3], b[j][0], xi[i][j]);
       }
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store_tiles(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
   }
 
   constexpr float inv_s = 1.0f / Tr::S;
