@@ -151,6 +151,52 @@ def graph_sample(binding, torch, stream, m_big, plan_big) -> dict:
     return out
 
 
+def multi_expect_sample(binding, torch, stream) -> dict:
+    """Energies of 8 fragment states (12-20 qubits, D = 16 or 32, each with its
+    own random-integral JW Hamiltonian) evaluated one call per state and in
+    one mps_expect_pauli_sum_multi pass, whose environment launches of equal
+    depth are shared by the states; the energies must agree bit for bit."""
+    from workloads import brickwork_gates, fuse_gates, hf_bits, jw_hamiltonian, pack_gates, \
+        random_integrals, workload_rng
+    states, plans = [], []
+    for i in range(8):
+        n_s = (6, 8, 10)[i % 3]
+        n = 2 * n_s
+        D = (16, 32)[i % 2]
+        h, g = random_integrals(n_s, workload_rng(3, 0, 200 + i))
+        ps = jw_hamiltonian(h, g)
+        ang = workload_rng(3, 1, 200 + i).uniform(-np.pi, np.pi, size=(6, n, 2))
+        m = binding.Mps(n, D, 1e-10, bits=hf_bits(n, n_s), stream=stream.cuda_stream)
+        m.apply_gates(*pack_gates(fuse_gates(brickwork_gates(n, ang), n)))
+        states.append(m)
+        plans.append(binding.PauliSum(ps.codes, ps.coeffs))
+    out = {"fragments": [{"qubits": m.n, "max_bond": int(m.bond_dims().max()), "strings": p.n_terms}
+                         for m, p in zip(states, plans)]}
+    reps = 20
+    for prec in ("c64", "c128"):
+        one = [m.expect(p, prec) for m, p in zip(states, plans)]  # set-up (untimed)
+        multi = binding.expect_multi(states, plans, prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            one = [m.expect(p, prec) for m, p in zip(states, plans)]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(reps):
+            multi = binding.expect_multi(states, plans, prec)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        row = {"one_by_one_ms": 1e3 * (t2 - t1) / reps, "shared_launches_ms": 1e3 * (t3 - t2) / reps,
+               "bitwise_equal": bool(all(a == b for a, b in zip(one, multi)))}
+        out[prec] = row
+        log(f"multi-state sample {prec}: one by one {row['one_by_one_ms']:.2f} ms, "
+            f"shared launches {row['shared_launches_ms']:.2f} ms, equal {row['bitwise_equal']}")
+    for m, p in zip(states, plans):
+        m.close()
+        p.close()
+    return out
+
+
 def gradient_sample(binding, stream) -> dict:
     """One parameter-shift gradient of the 8-qubit UCCSD workload (26
     parameters, 160 Pauli exponentials) with circuit-prefix caching: 321
@@ -432,6 +478,7 @@ def main():
         }
     graphs = None if args.no_extras else graph_sample(binding, torch, stream, m, plan)
     grad_sample = None if args.no_extras else gradient_sample(binding, stream)
+    multi_sample = None if args.no_extras else multi_expect_sample(binding, torch, stream)
     e_ref = precisions["c128"]["energy"] if "c128" in precisions else e_head
     for pr, d in precisions.items():
         d["abs_dE_vs_c128"] = abs(d["energy"] - e_ref)
@@ -493,6 +540,7 @@ def main():
         "plan": st,
         "autotune": autotune_summary(binding, not args.no_autotune),
         "expect_graph_vs_eager": graphs,
+        "expect_multi_state": multi_sample,
         "gradient_step": grad_sample,
         "bond_dims_max": int(dims.max()),
         "discarded_weight": disc,

@@ -256,6 +256,25 @@ mps_status mps_expect_pauli_rows(mps_handle h, mps_pauli_sum p, mps_precision pr
 mps_status mps_expect_pauli_sums(mps_handle h, int32_t n_plans, const mps_pauli_sum* plans,
                                  mps_precision prec, double* energy, double* per_term);
 
+/* Several states, each with its own plan (plans[i] for states[i], e.g. the
+ * fragments of a DMET-like decomposition; Methods, heterogeneous
+ * parallelization: fragments are independent), evaluated together as
+ * mps_expect_pauli_sum would evaluate each (Eqs. expec1, expec2, the same
+ * roots, boundary environments and normalisation).  The environment updates
+ * of equal depth in the states' launch sequences run as one launch per GEMM
+ * half, every item carrying its own site tensor and dims, on states[0]'s
+ * stream, so count states take the launches of the deepest one instead of
+ * the sum; the closing traces, string values and compensated energies follow
+ * per state.  energies[i] receives state i's E; per_term (may be NULL, as may
+ * any per_term[i]) receives Re<P_k> of plan i.  The values equal those of
+ * count separate calls bit for bit (every tile shape accumulates in the same
+ * order).  The other states' streams are synchronised after their set-up;
+ * the call returns after the work is done.  Tile autotuning, graph replay and
+ * per-state timing do not apply.  MPS_ERR_ARG for count < 0, NULL arrays or
+ * plans, repeated states or a qubit-count mismatch; count = 0 is a no-op. */
+mps_status mps_expect_pauli_sum_multi(int32_t count, const mps_handle* states, const mps_pauli_sum* plans,
+                                      mps_precision prec, double* energies, double* const* per_term);
+
 /* The state as a dense vector (Eq. mps: c_{i_1..i_N} = B^{i_1} ... B^{i_N},
  * contracted site by site on the device): psi receives 2^N complex
  * amplitudes as (re, im) pairs, qubit 0 the most significant bit of the

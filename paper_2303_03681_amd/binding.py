@@ -113,6 +113,7 @@ _SIGS = {
     "mps_device_bytes": [_P, _P],
     "mps_selftest_mfma": [_P],
     "mps_expect_pauli_sums": [_P, _I32, _P, C.c_int, _P, _P],
+    "mps_expect_pauli_sum_multi": [_I32, _P, _P, C.c_int, _P, _P],
     "mps_to_statevector": [_P, _P],
     "mps_jacobi_svd_noalloc": [_I32, _I32, _P, _P, _P, _P, _P],
 }
@@ -403,6 +404,23 @@ def apply_gates_multi(mpss, gate_lists, stream=None) -> np.ndarray:
         err.n_done = done
         raise
     return done
+
+
+def expect_multi(states, plans, prec: str = "c128", per_term: bool = False):
+    """E of every (state, plan) pair in one pass: environment launches of equal
+    depth are shared by all states.  Returns an array of energies (and the
+    per-string values of each plan)."""
+    n = len(states)
+    if len(plans) != n:
+        raise ValueError("one plan per state")
+    lib = load()
+    hs = (C.c_void_p * n)(*[m._h for m in states])
+    ps = (C.c_void_p * n)(*[p._h for p in plans])
+    e = np.zeros(n, np.float64)
+    outs = [np.zeros(p.n_terms, np.float64) for p in plans] if per_term else None
+    pt = (C.c_void_p * n)(*[o.ctypes.data for o in outs]) if per_term else None
+    _check(lib.mps_expect_pauli_sum_multi(n, hs, ps, PREC[prec], _ptr(e), pt))
+    return (e, outs) if per_term else e
 
 
 def jacobi_svd(vectors: np.ndarray):

@@ -86,16 +86,22 @@ struct CanonRightItem {   // W[alpha][(s,b')] = sum_beta A[s][alpha][beta] T[bet
 };
 
 // ---------------------------------------------------------------- environments
+// `site` null: the launch's site tensor and dims (one MPS per launch); set:
+// this item's own (launches shared by several MPSs).
 template <typename C2>
 struct EnvParent {        // X = L [A^0 | A^1]
   const C2* l;            // (Dl x Dl)
   C2* x;                  // (Dl x 2Dr)
+  const C2* site;
+  int dl, dr;
 };
 template <typename C2>
 struct EnvChild {         // L' = sum_s A^{s+} (ph_s X^{s xor flip})
   const C2* x;
   C2* out;                // (Dr x Dr)
   int letter;             // 0 I, 1 X, 2 Y, 3 Z
+  int dl, dr;
+  const C2* site;
 };
 
 struct GramItem {         // G[a][b] = Re sum_x L_a[x] R_b[x]  (closing traces at one bond)

@@ -1201,7 +1201,8 @@ hipError_t launch_fill_ident(double2* dst, int d, hipStream_t s) {
 
 // =================================================================== Eq. (expec2)
 
-// X = L [A^0 | A^1]: (Dl x Dl)(Dl x 2Dr); shared site A, one item per parent.
+// X = L [A^0 | A^1]: (Dl x Dl)(Dl x 2Dr); one item per parent, the site A and
+// the dims the launch's or (items of several MPSs in one launch) the item's.
 template <typename TT>
 struct EnvG1P {
   using T = TT;
@@ -1218,6 +1219,7 @@ struct EnvG1P {
   int dl, dr;
   __device__ Ctx context(int i) const {
     const EnvParent<C2> e = items[i];
+    if (e.site) return Ctx{e.l, e.x, e.site, e.dl, e.dr};
     return Ctx{e.l, e.x, site, dl, dr};
   }
   __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {
@@ -1260,6 +1262,7 @@ struct EnvG2P {
   int dl, dr;
   __device__ Ctx context(int i) const {
     const EnvChild<C2> e = items[i];
+    if (e.site) return Ctx{e.x, e.out, e.site, e.dl, e.dr, e.letter};
     return Ctx{e.x, e.out, site, dl, dr, e.letter};
   }
   __device__ static void dims(const Ctx& c, int& M, int& N, int& K) {

@@ -87,6 +87,8 @@ struct ExpectSetup {
   size_t xbuf_bytes = 0;
   void* desc = nullptr;        // all descriptors
   size_t desc_bytes = 0;
+  std::vector<char> host_desc; // host copy of the descriptors (environment launches of several MPSs)
+  int64_t plan_terms = 0;
   double* gbuf = nullptr;      // closing traces
   size_t gbuf_count = 0;
   double* gpart = nullptr;     // split-K partial tiles of the closing traces
@@ -1394,6 +1396,8 @@ mps_status build_expect(mps_state* h, const mps_psum* ps, int prec) {
   }
   if (!gram.empty()) std::memcpy(host.data() + ex.gram_off, gram.data(), gram.size() * sizeof(GramItem));
   HIP_TRY(h, hipMemcpy(ex.desc, host.data(), host.size(), hipMemcpyHostToDevice));
+  ex.host_desc = host;
+  ex.plan_terms = T;
   if (T) {
     HIP_TRY(h, hipMemcpy(ex.gidx, gidx.data(), T * sizeof(int64_t), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(ex.coeffs, P.coeffs.data(), T * sizeof(double), hipMemcpyHostToDevice));
@@ -1571,10 +1575,12 @@ struct RowsSpec {
 
 // pair_out (device, may be null) receives the energy's compensated (sum,
 // error) pair, for sums over several plans added on the device.
-mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
-                       double* per_term, const RowsSpec* rows = nullptr, double* pair_out = nullptr) {
+// The expectation's set-up on h's stream: the plan's device layout, the site
+// tensors in environment precision (and transposed), the trie roots.  *nrm:
+// the device value <psi|psi> to divide by (boundary environments), or null in
+// exact canonical form.
+mps_status expect_open(mps_state* h, const mps_psum* ps, int prec, const double2** nrm_out) {
   mps_status st;
-  const double t0 = now_ms();
   if ((st = build_expect(h, ps, prec)) != MPS_OK) return st;
   ExpectSetup& ex = h->ex;
   const int el = prec == MPS_PREC_C128 ? 16 : 8;
@@ -1605,6 +1611,32 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
     for (const auto& r : ex.roots)
       HIP_TRY(h, launch_roots(h->lcur(r.bond), r.lroot, r.rroot, r.d, el, h->stream));
   }
+  *nrm_out = nrm;
+  return MPS_OK;
+}
+
+// The closing traces (a11), per-string values normalised by *nrm (a9) and the
+// compensated energy (a12) of h's current plan, on stream s.
+mps_status expect_close(mps_state* h, int el, const double2* nrm, hipStream_t s) {
+  const ExpectSetup& ex = h->ex;
+  const int64_t T = ex.plan_terms;
+  HIP_TRY(h, launch_gram((const GramItem*)((char*)ex.desc + ex.gram_off),
+                         (const GramTile*)((char*)ex.desc + ex.tiles_off), ex.gram_tiles, el, ex.gpart,
+                         ex.gram_split, s));
+  HIP_TRY(h, launch_gather(ex.gbuf, ex.gidx, nrm, ex.per_term, T, s));
+  HIP_TRY(h, launch_energy(ex.per_term, ex.coeffs, T, ex.energy, s));
+  return MPS_OK;
+}
+
+mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energy,
+                       double* per_term, const RowsSpec* rows = nullptr, double* pair_out = nullptr) {
+  mps_status st;
+  const double t0 = now_ms();
+  const double2* nrm = nullptr;
+  if ((st = expect_open(h, ps, prec, &nrm)) != MPS_OK) return st;
+  ExpectSetup& ex = h->ex;
+  const int el = prec == MPS_PREC_C128 ? 16 : 8;
+  const bool chains = nrm != nullptr;
   std::vector<TunePending> pending;
   h->ev_tune_used = 0;
   const int64_t T = ps->plan.n_terms;
@@ -1712,6 +1744,136 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   if (nrm) h->norm = std::sqrt(nn.x);
   *energy = E2[0] + E2[1];
   h->tm.expect_ms += now_ms() - t0;
+  return MPS_OK;
+}
+
+// Several MPSs, each with its own plan, evaluated together: after each
+// state's set-up, the environment launches of equal depth in the states'
+// sequences become one launch per GEMM half (every item carries its own site
+// tensor and dims), on the first state's stream; then each state's closes,
+// gather and energy.  Per-element accumulation order is that of the
+// single-state path (every tile shape takes K in the same 16x16x4 steps), so
+// the values equal those of one expectation per state bit for bit.
+mps_status expect_multi_impl(mps_state* const* hs, const mps_psum* const* ps, int count, int prec,
+                             double* energies, double* const* per_term) {
+  mps_state* drv = hs[0];
+  const int el = prec == MPS_PREC_C128 ? 16 : 8;
+  const double t0 = now_ms();
+  mps_status st;
+  std::vector<const double2*> nrm(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    if ((st = expect_open(hs[i], ps[i], prec, &nrm[i])) != MPS_OK) return st;
+    if (hs[i]->stream != drv->stream && (st = sync(hs[i])) != MPS_OK) return st;
+  }
+  // merged launches: [left depth 0, 1, ...][right depth 0, 1, ...]
+  struct Merged {
+    size_t par_off, chi_off;
+    int n_par, n_chi, max_dl, max_dr;
+  };
+  using P = EnvParent<double2>;  // pointer layout shared by every precision
+  using Ch = EnvChild<double2>;
+  std::vector<char> blob;
+  auto put = [&](size_t bytes) {
+    const size_t o = blob.size();
+    blob.resize(o + ((bytes + 255) & ~(size_t)255));
+    return o;
+  };
+  std::vector<Merged> merged;
+  for (int pass = 0; pass < 2; ++pass) {
+    size_t depth = 0;
+    for (int i = 0; i < count; ++i) {
+      const auto& ls = pass == 0 ? hs[i]->ex.left_launches : hs[i]->ex.right_launches;
+      depth = std::max(depth, ls.size());
+    }
+    for (size_t t = 0; t < depth; ++t) {
+      Merged M{0, 0, 0, 0, 0, 0};
+      for (int i = 0; i < count; ++i) {
+        const auto& ls = pass == 0 ? hs[i]->ex.left_launches : hs[i]->ex.right_launches;
+        if (t < ls.size()) {
+          M.n_par += ls[t].n_parents;
+          M.n_chi += ls[t].n_children;
+        }
+      }
+      M.par_off = put(sizeof(P) * M.n_par);
+      M.chi_off = put(sizeof(Ch) * M.n_chi);
+      P* pp = (P*)(blob.data() + M.par_off);
+      Ch* cp = (Ch*)(blob.data() + M.chi_off);
+      for (int i = 0; i < count; ++i) {
+        mps_state* h = hs[i];
+        const auto& ls = pass == 0 ? h->ex.left_launches : h->ex.right_launches;
+        if (t >= ls.size()) continue;
+        const ExpectSetup::EnvLaunch& L = ls[t];
+        // the site tensor the single-state launch would take (run_env_launch)
+        const void* site = L.left ? (h->ex.prep[L.site].fwd ? h->ex.prep[L.site].fwd
+                                                            : (const void*)h->cur(L.site))
+                                  : h->ex.prep[L.site].tr;
+        const P* sp = (const P*)(h->ex.host_desc.data() + L.parents_off);
+        const Ch* sc = (const Ch*)(h->ex.host_desc.data() + L.children_off);
+        for (int k = 0; k < L.n_parents; ++k) {
+          *pp = sp[k];
+          pp->site = (const double2*)site;
+          pp->dl = L.dl;
+          pp->dr = L.dr;
+          ++pp;
+        }
+        for (int k = 0; k < L.n_children; ++k) {
+          *cp = sc[k];
+          cp->site = (const double2*)site;
+          cp->dl = L.dl;
+          cp->dr = L.dr;
+          ++cp;
+        }
+        M.max_dl = std::max(M.max_dl, L.dl);
+        M.max_dr = std::max(M.max_dr, L.dr);
+      }
+      merged.push_back(M);
+    }
+  }
+  if ((st = ensure_desc(drv, blob.size() + 256)) != MPS_OK) return st;
+  char* d = (char*)drv->d_desc;
+  if ((st = upload(drv, d, blob.data(), blob.size())) != MPS_OK) return st;
+  for (const Merged& M : merged) {
+    const P* dp = (const P*)(d + M.par_off);
+    const Ch* dc = (const Ch*)(d + M.chi_off);
+    // launch-level site null: every item names its own; the dims size the grid
+    if (prec == MPS_PREC_C128) {
+      HIP_TRY(drv, launch_env_gemm1_c128(dp, M.n_par, nullptr, M.max_dl, M.max_dr, drv->stream, 0));
+      HIP_TRY(drv, launch_env_gemm2_c128(dc, M.n_chi, nullptr, M.max_dl, M.max_dr, drv->stream, 0));
+    } else if (prec == MPS_PREC_C64) {
+      HIP_TRY(drv, launch_env_gemm1_c64((const EnvParent<float2>*)dp, M.n_par, nullptr, M.max_dl, M.max_dr,
+                                        drv->stream, 0));
+      HIP_TRY(drv, launch_env_gemm2_c64((const EnvChild<float2>*)dc, M.n_chi, nullptr, M.max_dl, M.max_dr,
+                                        drv->stream, 0));
+    } else {
+      const int f16 = prec == MPS_PREC_SPLIT_F16;
+      HIP_TRY(drv, launch_env_gemm1_split((const EnvParent<float2>*)dp, M.n_par, nullptr, M.max_dl, M.max_dr,
+                                          f16, drv->stream));
+      HIP_TRY(drv, launch_env_gemm2_split((const EnvChild<float2>*)dc, M.n_chi, nullptr, M.max_dl, M.max_dr,
+                                          f16, drv->stream));
+    }
+  }
+  if (drv->timing) drv->tm.env_launches += 2 * (int64_t)merged.size();
+  std::vector<double> e2(2 * (size_t)count, 0.0);
+  std::vector<double2> nn(count, make_double2(1.0, 0.0));
+  for (int i = 0; i < count; ++i) {
+    mps_state* h = hs[i];
+    if ((st = expect_close(h, el, nrm[i], drv->stream)) != MPS_OK) return st;
+    HIP_TRY(drv, hipMemcpyAsync(e2.data() + 2 * i, h->ex.energy, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                drv->stream));
+    if (nrm[i])
+      HIP_TRY(drv, hipMemcpyAsync(&nn[i], nrm[i], sizeof(double2), hipMemcpyDeviceToHost, drv->stream));
+    if (per_term && per_term[i] && h->ex.plan_terms)
+      HIP_TRY(drv, hipMemcpyAsync(per_term[i], h->ex.per_term, sizeof(double) * h->ex.plan_terms,
+                                  hipMemcpyDeviceToHost, drv->stream));
+  }
+  if ((st = sync(drv)) != MPS_OK) return st;
+  for (int i = 0; i < count; ++i) {
+    if (!(nn[i].x > 0.0) || !std::isfinite(nn[i].x))
+      return fail(MPS_ERR_NONFINITE, "state " + std::to_string(i) + ": norm is zero or not finite");
+    if (nrm[i]) hs[i]->norm = std::sqrt(nn[i].x);
+    energies[i] = e2[2 * i] + e2[2 * i + 1];
+  }
+  drv->tm.expect_ms += now_ms() - t0;
   return MPS_OK;
 }
 
@@ -2311,6 +2473,26 @@ mps_status mps_expect_pauli_sum(mps_handle h, mps_pauli_sum p, mps_precision pre
       prec != MPS_PREC_SPLIT_F16)
     return fail(MPS_ERR_ARG, "unknown precision");
   return expect_impl(h, p, (int)prec, energy, per_term);
+}
+
+mps_status mps_expect_pauli_sum_multi(int32_t count, const mps_handle* states, const mps_pauli_sum* plans,
+                                      mps_precision prec, double* energies, double* const* per_term) {
+  if (count < 0) return fail(MPS_ERR_ARG, "count < 0");
+  if (count == 0) return MPS_OK;
+  if (!states || !plans || !energies) return fail(MPS_ERR_ARG, "NULL array");
+  if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64 && prec != MPS_PREC_SPLIT_BF16 &&
+      prec != MPS_PREC_SPLIT_F16)
+    return fail(MPS_ERR_ARG, "unknown precision");
+  for (int32_t i = 0; i < count; ++i) {
+    mps_status st = check_handle(states[i]);
+    if (st != MPS_OK) return st;
+    for (int32_t j = 0; j < i; ++j)
+      if (states[j] == states[i]) return fail(MPS_ERR_ARG, "states must be distinct");
+    if (!plans[i]) return fail(MPS_ERR_ARG, "NULL plan");
+    if (plans[i]->plan.n_qubits != states[i]->n)
+      return fail(MPS_ERR_ARG, "state " + std::to_string(i) + ": plan and MPS qubit counts differ");
+  }
+  return expect_multi_impl(states, plans, count, (int)prec, energies, per_term);
 }
 
 mps_status mps_expect_pauli_rows(mps_handle h, mps_pauli_sum p, mps_precision prec, int64_t n_rows,

@@ -159,6 +159,12 @@ class GpuBackend:
     def expect(self, handle, frag: Fragment) -> float:
         return handle.expect(self._plan(frag), self.prec)
 
+    def expect_many(self, pairs):
+        """Energies of several (handle, fragment) pairs in one pass: their
+        environment updates of equal depth share launches."""
+        return list(self.binding.expect_multi([h for h, _ in pairs], [self._plan(f) for _, f in pairs],
+                                              self.prec))
+
     def gradient(self, frag: Fragment, update: int):
         """Energy and parameter-shift gradient of the fragment's UCCSD at the
         update's angles (f1); the gradient engine and its handles are kept
@@ -348,7 +354,16 @@ class Server:
                 r.update == next_update[r.fid] and r.fid not in self.busy for r in waiting[:1])
             waiting = still
             max_seen = max(max_seen, in_flight)
-            # 2. energies of requests whose gates are done; gradient requests
+            # 2. energies of requests whose gates are done (together, when the
+            #    backend can share their launches); gradient requests
+            many = getattr(self.backend, "expect_many", None)
+            if many is not None and len(ready) > 1:
+                try:
+                    for a, e in zip(ready, many([(a.handle, a.frag) for a in ready])):
+                        finish(a, e)
+                    ready = []
+                except Exception:
+                    pass  # one at a time below, so that an error names its request
             for a in ready:
                 try:
                     finish(a, self.backend.expect(a.handle, a.frag))
