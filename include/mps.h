@@ -264,14 +264,16 @@ mps_status mps_expect_pauli_sums(mps_handle h, int32_t n_plans, const mps_pauli_
  * of equal depth in the states' launch sequences run as one launch per GEMM
  * half, every item carrying its own site tensor and dims, on states[0]'s
  * stream, so count states take the launches of the deepest one instead of
- * the sum; the closing traces, string values and compensated energies follow
- * per state.  energies[i] receives state i's E; per_term (may be NULL, as may
+ * the sum; so do the set-up steps (site tensors in environment precision,
+ * each depth of the boundary-environment chains, the roots).  The closing
+ * traces, string values and compensated energies follow per state.  energies[i] receives state i's E; per_term (may be NULL, as may
  * any per_term[i]) receives Re<P_k> of plan i.  The values equal those of
  * count separate calls bit for bit (every tile shape accumulates in the same
  * order).  The other states' streams are synchronised after their set-up;
  * the call returns after the work is done.  Tile autotuning, graph replay and
  * per-state timing do not apply.  MPS_ERR_ARG for count < 0, NULL arrays or
- * plans, repeated states or a qubit-count mismatch; count = 0 is a no-op. */
+ * plans, repeated states, a qubit-count mismatch or more than 32767 sites
+ * (qubits + 1 per state) in one call; count = 0 is a no-op. */
 mps_status mps_expect_pauli_sum_multi(int32_t count, const mps_handle* states, const mps_pauli_sum* plans,
                                       mps_precision prec, double* energies, double* const* per_term);
 

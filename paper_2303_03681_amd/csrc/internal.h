@@ -210,6 +210,21 @@ hipError_t launch_env_gemm2_split(const EnvChild<float2>* items, int count, cons
 hipError_t launch_site_prepare(const double2* site, void* out_fwd, void* out_tr, int dl, int dr,
                                int elem_bytes, hipStream_t s);
 hipError_t launch_root_copy(const double2* src, void* dst, size_t count, int elem_bytes, hipStream_t s);
+struct PrepItem {         // one site tensor to prepare (fwd may be null), as launch_site_prepare
+  const double2* site;
+  void* fwd;
+  void* tr;
+  int dl, dr;
+};
+struct CopyItem {         // one FP64 environment to copy into a root slot, as launch_root_copy
+  const double2* src;
+  void* dst;
+  long long count;
+};
+hipError_t launch_site_prepare_list(const PrepItem* items, int count, int max_elems, int elem_bytes,
+                                    hipStream_t s);
+hipError_t launch_root_copy_list(const CopyItem* items, int count, long long max_count, int elem_bytes,
+                                 hipStream_t s);
 hipError_t launch_roots(const double* lam, void* lroot, void* rroot, int d, int elem_bytes,
                         hipStream_t s);
 int gram_splits(int max_kdim);  // K splits of the closing-trace tiles

@@ -1441,6 +1441,61 @@ hipError_t launch_root_copy(const double2* src, void* dst, size_t count, int ele
   return hipGetLastError();
 }
 
+// Lists of the two kernels above in one launch each (several states'
+// set-up): block row y takes item y, 256 elements per block along x.
+template <typename C2>
+__global__ void site_prepare_list_kernel(const PrepItem* items) {
+  const PrepItem it = items[blockIdx.y];
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int per = it.dl * it.dr;
+  if (idx >= 2 * per) return;
+  const int s = idx / per;
+  const int rem = idx - s * per;
+  const int a = rem / it.dr, b = rem - (rem / it.dr) * it.dr;
+  const double2 v = it.site[idx];
+  C2 o;
+  o.x = v.x;
+  o.y = v.y;
+  if (it.fwd) ((C2*)it.fwd)[idx] = o;
+  ((C2*)it.tr)[(size_t)s * per + (size_t)b * it.dl + a] = o;
+}
+
+hipError_t launch_site_prepare_list(const PrepItem* items, int count, int max_elems, int elem_bytes,
+                                    hipStream_t s) {
+  if (count <= 0 || max_elems <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  const dim3 grid(cdiv((long long)max_elems, 256), count);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(site_prepare_list_kernel<double2>, grid, dim3(256), 0, s, items);
+  else
+    hipLaunchKernelGGL(site_prepare_list_kernel<float2>, grid, dim3(256), 0, s, items);
+  return hipGetLastError();
+}
+
+template <typename C2>
+__global__ void root_copy_list_kernel(const CopyItem* items) {
+  const CopyItem it = items[blockIdx.y];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < it.count) {
+    C2 v;
+    v.x = it.src[i].x;
+    v.y = it.src[i].y;
+    ((C2*)it.dst)[i] = v;
+  }
+}
+
+hipError_t launch_root_copy_list(const CopyItem* items, int count, long long max_count, int elem_bytes,
+                                 hipStream_t s) {
+  if (count <= 0 || max_count <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  const dim3 grid(cdiv(max_count, 256), count);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(root_copy_list_kernel<double2>, grid, dim3(256), 0, s, items);
+  else
+    hipLaunchKernelGGL(root_copy_list_kernel<float2>, grid, dim3(256), 0, s, items);
+  return hipGetLastError();
+}
+
 // Closing traces: Tr(L_a R_b) = sum_{xy} L_a[x][y] R_b[y][x] = sum_x L_a[x] R^T_b[x]
 // with right environments stored transposed; computed in FP64, real part
 // only, for the 64x64 tiles of (prefix, suffix) pairs that some string needs.

@@ -155,6 +155,7 @@ struct mps_state {
   double2* d_lchain = nullptr;
   double2* d_rchain = nullptr;
   double2* d_chainx = nullptr;  // GEMM1 output of one chain step
+  double2* d_chainxr = nullptr; // ... of the right chain
   double2* d_chaintr = nullptr; // one site tensor, transposed, for the right chain
   void* d_chaindesc = nullptr;
   std::vector<size_t> chain_off;
@@ -945,7 +946,7 @@ mps_status canonicalize_impl(mps_state* h) {
 // when the sites are not in exact canonical form.  Slots and descriptors are
 // laid out once by bond capacity; the chains are recomputed only after the
 // state changed (e.g. several Pauli sums, or chunks of one, on one state).
-mps_status identity_chains(mps_state* h, int rmin) {
+mps_status ensure_chain_buffers(mps_state* h) {
   const int n = h->n;
   mps_status st;
   using P = EnvParent<double2>;
@@ -1000,10 +1001,20 @@ mps_status identity_chains(mps_state* h, int rmin) {
     h->d_lchain = lc;
     h->d_rchain = rc;
     h->d_chainx = cx;
+    h->d_chainxr = cxr;
     h->d_chaintr = ctr;
     h->d_chaindesc = desc;
     h->chain_off = off;
   }
+  return MPS_OK;
+}
+
+mps_status identity_chains(mps_state* h, int rmin) {
+  const int n = h->n;
+  mps_status st;
+  using P = EnvParent<double2>;
+  using Ch = EnvChild<double2>;
+  if ((st = ensure_chain_buffers(h)) != MPS_OK) return st;
   if (h->chain_version == h->version && h->chain_rmin <= rmin) return MPS_OK;  // still current
   const P* lp = (const P*)h->d_chaindesc;
   const Ch* lch = (const Ch*)(lp + n);
@@ -1747,13 +1758,17 @@ mps_status expect_impl(mps_state* h, const mps_psum* ps, int prec, double* energ
   return MPS_OK;
 }
 
-// Several MPSs, each with its own plan, evaluated together: after each
-// state's set-up, the environment launches of equal depth in the states'
-// sequences become one launch per GEMM half (every item carries its own site
-// tensor and dims), on the first state's stream; then each state's closes,
-// gather and energy.  Per-element accumulation order is that of the
-// single-state path (every tile shape takes K in the same 16x16x4 steps), so
-// the values equal those of one expectation per state bit for bit.
+// Several MPSs, each with its own plan, evaluated together, every step that
+// launches per site or per trie node merged over the states: one launch
+// prepares all states' site tensors, each depth of the boundary-environment
+// chains (FP64, Eq. expec2 with identity letters) is one launch per GEMM half
+// for all states whose chains are stale, one launch fills all roots, and the
+// environment updates of equal depth in the states' trie sequences are one
+// launch per GEMM half (every item carries its own site tensor and dims);
+// then each state's closes, gather and energy.  All on the first state's
+// stream.  Per-element accumulation order is that of the single-state path
+// (every tile shape takes K in the same 16x16x4 steps), so the values equal
+// those of one expectation per state bit for bit.
 mps_status expect_multi_impl(mps_state* const* hs, const mps_psum* const* ps, int count, int prec,
                              double* energies, double* const* per_term) {
   mps_state* drv = hs[0];
@@ -1761,24 +1776,113 @@ mps_status expect_multi_impl(mps_state* const* hs, const mps_psum* const* ps, in
   const double t0 = now_ms();
   mps_status st;
   std::vector<const double2*> nrm(count, nullptr);
+  std::vector<int> rmin(count, 0), stale(count, 0);
+  int max_n = 0;
   for (int i = 0; i < count; ++i) {
-    if ((st = expect_open(hs[i], ps[i], prec, &nrm[i])) != MPS_OK) return st;
-    if (hs[i]->stream != drv->stream && (st = sync(hs[i])) != MPS_OK) return st;
+    mps_state* h = hs[i];
+    if ((st = build_expect(h, ps[i], prec)) != MPS_OK) return st;
+    if (h->stream != drv->stream && (st = sync(h)) != MPS_OK) return st;  // h's earlier work done
+    max_n = std::max(max_n, h->n);
+    if (h->canonical) continue;
+    if ((st = ensure_chain_buffers(h)) != MPS_OK) return st;
+    rmin[i] = h->n;
+    for (const auto& r : h->ex.roots)
+      if (r.rroot) rmin[i] = std::min(rmin[i], r.bond);
+    stale[i] = !(h->chain_version == h->version && h->chain_rmin <= rmin[i]);
+    nrm[i] = h->d_lchain + h->chain_off[h->n];
   }
-  // merged launches: [left depth 0, 1, ...][right depth 0, 1, ...]
-  struct Merged {
-    size_t par_off, chi_off;
-    int n_par, n_chi, max_dl, max_dr;
-  };
   using P = EnvParent<double2>;  // pointer layout shared by every precision
   using Ch = EnvChild<double2>;
   std::vector<char> blob;
-  auto put = [&](size_t bytes) {
+  auto put = [&](const void* src, size_t bytes) {
     const size_t o = blob.size();
     blob.resize(o + ((bytes + 255) & ~(size_t)255));
+    if (src && bytes) std::memcpy(blob.data() + o, src, bytes);
     return o;
   };
-  std::vector<Merged> merged;
+  struct Gemms {  // one merged launch per GEMM half
+    size_t par_off = 0, chi_off = 0;
+    int n_par = 0, n_chi = 0, max_dl = 0, max_dr = 0;
+  };
+  struct Preps {
+    size_t off = 0;
+    int n = 0, max_elems = 0;
+  };
+  auto put_preps = [&](const std::vector<PrepItem>& v) {
+    Preps r;
+    r.n = (int)v.size();
+    for (const PrepItem& it : v) r.max_elems = std::max(r.max_elems, 2 * it.dl * it.dr);
+    r.off = put(v.data(), v.size() * sizeof(PrepItem));
+    return r;
+  };
+  auto put_gemms = [&](const std::vector<P>& par, const std::vector<Ch>& chi) {
+    Gemms g;
+    g.n_par = (int)par.size();
+    g.n_chi = (int)chi.size();
+    for (const P& x : par) {
+      g.max_dl = std::max(g.max_dl, x.dl);
+      g.max_dr = std::max(g.max_dr, x.dr);
+    }
+    g.par_off = put(par.data(), par.size() * sizeof(P));
+    g.chi_off = put(chi.data(), chi.size() * sizeof(Ch));
+    return g;
+  };
+  // (1) every state's sites in environment precision (and transposed)
+  std::vector<PrepItem> pv;
+  for (int i = 0; i < count; ++i)
+    for (int q = 0; q < hs[i]->n; ++q) {
+      const auto& pr = hs[i]->ex.prep[q];
+      pv.push_back(PrepItem{hs[i]->cur(q), pr.fwd, pr.tr, pr.dl, pr.dr});
+    }
+  const Preps site_preps = put_preps(pv);
+  // (2) boundary-environment chains of the stale states, depth by depth
+  std::vector<Gemms> left_chain;
+  for (int q = 0; q < max_n; ++q) {
+    std::vector<P> par;
+    std::vector<Ch> chi;
+    for (int i = 0; i < count; ++i) {
+      mps_state* h = hs[i];
+      if (!stale[i] || q >= h->n) continue;
+      const int dl = h->dims[q], dr = h->dims[q + 1];
+      double2* lc = h->d_lchain;
+      par.push_back(P{lc + h->chain_off[q], h->d_chainx, h->cur(q), dl, dr});
+      chi.push_back(Ch{h->d_chainx, lc + h->chain_off[q + 1], 0, dl, dr, h->cur(q)});
+    }
+    if (!par.empty()) left_chain.push_back(put_gemms(par, chi));
+  }
+  std::vector<std::pair<Preps, Gemms>> right_chain;
+  for (int t = 0; t < max_n; ++t) {
+    std::vector<PrepItem> tv;
+    std::vector<P> par;
+    std::vector<Ch> chi;
+    for (int i = 0; i < count; ++i) {
+      mps_state* h = hs[i];
+      const int q = h->n - 1 - t;
+      if (!stale[i] || q < rmin[i] || q < 0) continue;
+      const int dl = h->dims[q + 1], dr = h->dims[q];  // transposed form
+      double2* rc = h->d_rchain;
+      tv.push_back(PrepItem{h->cur(q), nullptr, h->d_chaintr, h->dims[q], h->dims[q + 1]});
+      par.push_back(P{rc + h->chain_off[q + 1], h->d_chainxr, h->d_chaintr, dl, dr});
+      chi.push_back(Ch{h->d_chainxr, rc + h->chain_off[q], 0, dl, dr, h->d_chaintr});
+    }
+    if (!par.empty()) right_chain.push_back({put_preps(tv), put_gemms(par, chi)});
+  }
+  // (3) roots from the chains
+  std::vector<CopyItem> cv;
+  long long copy_max = 0;
+  for (int i = 0; i < count; ++i) {
+    mps_state* h = hs[i];
+    if (h->canonical) continue;
+    for (const auto& r : h->ex.roots) {
+      const long long cnt = (long long)r.d * r.d;
+      if (r.lroot) cv.push_back(CopyItem{h->d_lchain + h->chain_off[r.bond], r.lroot, cnt});
+      if (r.rroot) cv.push_back(CopyItem{h->d_rchain + h->chain_off[r.bond], r.rroot, cnt});
+      copy_max = std::max(copy_max, cnt);
+    }
+  }
+  const size_t copy_off = put(cv.data(), cv.size() * sizeof(CopyItem));
+  // (4) environment updates of equal trie depth: [left depth 0, 1, ...][right depth 0, 1, ...]
+  std::vector<Gemms> env;
   for (int pass = 0; pass < 2; ++pass) {
     size_t depth = 0;
     for (int i = 0; i < count; ++i) {
@@ -1786,18 +1890,8 @@ mps_status expect_multi_impl(mps_state* const* hs, const mps_psum* const* ps, in
       depth = std::max(depth, ls.size());
     }
     for (size_t t = 0; t < depth; ++t) {
-      Merged M{0, 0, 0, 0, 0, 0};
-      for (int i = 0; i < count; ++i) {
-        const auto& ls = pass == 0 ? hs[i]->ex.left_launches : hs[i]->ex.right_launches;
-        if (t < ls.size()) {
-          M.n_par += ls[t].n_parents;
-          M.n_chi += ls[t].n_children;
-        }
-      }
-      M.par_off = put(sizeof(P) * M.n_par);
-      M.chi_off = put(sizeof(Ch) * M.n_chi);
-      P* pp = (P*)(blob.data() + M.par_off);
-      Ch* cp = (Ch*)(blob.data() + M.chi_off);
+      std::vector<P> par;
+      std::vector<Ch> chi;
       for (int i = 0; i < count; ++i) {
         mps_state* h = hs[i];
         const auto& ls = pass == 0 ? h->ex.left_launches : h->ex.right_launches;
@@ -1810,61 +1904,79 @@ mps_status expect_multi_impl(mps_state* const* hs, const mps_psum* const* ps, in
         const P* sp = (const P*)(h->ex.host_desc.data() + L.parents_off);
         const Ch* sc = (const Ch*)(h->ex.host_desc.data() + L.children_off);
         for (int k = 0; k < L.n_parents; ++k) {
-          *pp = sp[k];
-          pp->site = (const double2*)site;
-          pp->dl = L.dl;
-          pp->dr = L.dr;
-          ++pp;
+          P x = sp[k];
+          x.site = (const double2*)site;
+          x.dl = L.dl;
+          x.dr = L.dr;
+          par.push_back(x);
         }
         for (int k = 0; k < L.n_children; ++k) {
-          *cp = sc[k];
-          cp->site = (const double2*)site;
-          cp->dl = L.dl;
-          cp->dr = L.dr;
-          ++cp;
+          Ch x = sc[k];
+          x.site = (const double2*)site;
+          x.dl = L.dl;
+          x.dr = L.dr;
+          chi.push_back(x);
         }
-        M.max_dl = std::max(M.max_dl, L.dl);
-        M.max_dr = std::max(M.max_dr, L.dr);
       }
-      merged.push_back(M);
+      env.push_back(put_gemms(par, chi));
     }
   }
   if ((st = ensure_desc(drv, blob.size() + 256)) != MPS_OK) return st;
   char* d = (char*)drv->d_desc;
   if ((st = upload(drv, d, blob.data(), blob.size())) != MPS_OK) return st;
-  for (const Merged& M : merged) {
-    const P* dp = (const P*)(d + M.par_off);
-    const Ch* dc = (const Ch*)(d + M.chi_off);
-    // launch-level site null: every item names its own; the dims size the grid
-    if (prec == MPS_PREC_C128) {
-      HIP_TRY(drv, launch_env_gemm1_c128(dp, M.n_par, nullptr, M.max_dl, M.max_dr, drv->stream, 0));
-      HIP_TRY(drv, launch_env_gemm2_c128(dc, M.n_chi, nullptr, M.max_dl, M.max_dr, drv->stream, 0));
-    } else if (prec == MPS_PREC_C64) {
-      HIP_TRY(drv, launch_env_gemm1_c64((const EnvParent<float2>*)dp, M.n_par, nullptr, M.max_dl, M.max_dr,
-                                        drv->stream, 0));
-      HIP_TRY(drv, launch_env_gemm2_c64((const EnvChild<float2>*)dc, M.n_chi, nullptr, M.max_dl, M.max_dr,
-                                        drv->stream, 0));
-    } else {
-      const int f16 = prec == MPS_PREC_SPLIT_F16;
-      HIP_TRY(drv, launch_env_gemm1_split((const EnvParent<float2>*)dp, M.n_par, nullptr, M.max_dl, M.max_dr,
-                                          f16, drv->stream));
-      HIP_TRY(drv, launch_env_gemm2_split((const EnvChild<float2>*)dc, M.n_chi, nullptr, M.max_dl, M.max_dr,
-                                          f16, drv->stream));
+  hipStream_t s = drv->stream;
+  auto run_preps = [&](const Preps& p, int elem) -> hipError_t {
+    return launch_site_prepare_list((const PrepItem*)(d + p.off), p.n, p.max_elems, elem, s);
+  };
+  // launch-level site null: every item names its own; the dims size the grid
+  auto run_gemms = [&](const Gemms& g, int pr) -> hipError_t {
+    const P* dp = (const P*)(d + g.par_off);
+    const Ch* dc = (const Ch*)(d + g.chi_off);
+    hipError_t e;
+    if (pr == MPS_PREC_C128) {
+      e = launch_env_gemm1_c128(dp, g.n_par, nullptr, g.max_dl, g.max_dr, s, 0);
+      return e != hipSuccess ? e : launch_env_gemm2_c128(dc, g.n_chi, nullptr, g.max_dl, g.max_dr, s, 0);
     }
+    if (pr == MPS_PREC_C64) {
+      e = launch_env_gemm1_c64((const EnvParent<float2>*)dp, g.n_par, nullptr, g.max_dl, g.max_dr, s, 0);
+      return e != hipSuccess ? e
+                             : launch_env_gemm2_c64((const EnvChild<float2>*)dc, g.n_chi, nullptr, g.max_dl,
+                                                    g.max_dr, s, 0);
+    }
+    const int f16 = pr == MPS_PREC_SPLIT_F16;
+    e = launch_env_gemm1_split((const EnvParent<float2>*)dp, g.n_par, nullptr, g.max_dl, g.max_dr, f16, s);
+    return e != hipSuccess ? e
+                           : launch_env_gemm2_split((const EnvChild<float2>*)dc, g.n_chi, nullptr, g.max_dl,
+                                                    g.max_dr, f16, s);
+  };
+  HIP_TRY(drv, run_preps(site_preps, el));
+  for (const Gemms& g : left_chain) HIP_TRY(drv, run_gemms(g, MPS_PREC_C128));
+  for (const auto& rl : right_chain) {
+    HIP_TRY(drv, run_preps(rl.first, 16));
+    HIP_TRY(drv, run_gemms(rl.second, MPS_PREC_C128));
   }
-  if (drv->timing) drv->tm.env_launches += 2 * (int64_t)merged.size();
+  HIP_TRY(drv, launch_root_copy_list((const CopyItem*)(d + copy_off), (int)cv.size(), copy_max, el, s));
+  for (int i = 0; i < count; ++i)
+    if (hs[i]->canonical)
+      for (const auto& r : hs[i]->ex.roots)
+        HIP_TRY(drv, launch_roots(hs[i]->lcur(r.bond), r.lroot, r.rroot, r.d, el, s));
+  for (const Gemms& g : env) HIP_TRY(drv, run_gemms(g, prec));
+  for (int i = 0; i < count; ++i)
+    if (stale[i]) {
+      hs[i]->chain_version = hs[i]->version;
+      hs[i]->chain_rmin = rmin[i];
+    }
+  if (drv->timing) drv->tm.env_launches += 2 * (int64_t)env.size();
   std::vector<double> e2(2 * (size_t)count, 0.0);
   std::vector<double2> nn(count, make_double2(1.0, 0.0));
   for (int i = 0; i < count; ++i) {
     mps_state* h = hs[i];
-    if ((st = expect_close(h, el, nrm[i], drv->stream)) != MPS_OK) return st;
-    HIP_TRY(drv, hipMemcpyAsync(e2.data() + 2 * i, h->ex.energy, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                                drv->stream));
-    if (nrm[i])
-      HIP_TRY(drv, hipMemcpyAsync(&nn[i], nrm[i], sizeof(double2), hipMemcpyDeviceToHost, drv->stream));
+    if ((st = expect_close(h, el, nrm[i], s)) != MPS_OK) return st;
+    HIP_TRY(drv, hipMemcpyAsync(e2.data() + 2 * i, h->ex.energy, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (nrm[i]) HIP_TRY(drv, hipMemcpyAsync(&nn[i], nrm[i], sizeof(double2), hipMemcpyDeviceToHost, s));
     if (per_term && per_term[i] && h->ex.plan_terms)
       HIP_TRY(drv, hipMemcpyAsync(per_term[i], h->ex.per_term, sizeof(double) * h->ex.plan_terms,
-                                  hipMemcpyDeviceToHost, drv->stream));
+                                  hipMemcpyDeviceToHost, s));
   }
   if ((st = sync(drv)) != MPS_OK) return st;
   for (int i = 0; i < count; ++i) {
@@ -2483,15 +2595,19 @@ mps_status mps_expect_pauli_sum_multi(int32_t count, const mps_handle* states, c
   if (prec != MPS_PREC_C128 && prec != MPS_PREC_C64 && prec != MPS_PREC_SPLIT_BF16 &&
       prec != MPS_PREC_SPLIT_F16)
     return fail(MPS_ERR_ARG, "unknown precision");
+  int64_t sites = 0;
   for (int32_t i = 0; i < count; ++i) {
     mps_status st = check_handle(states[i]);
     if (st != MPS_OK) return st;
     for (int32_t j = 0; j < i; ++j)
       if (states[j] == states[i]) return fail(MPS_ERR_ARG, "states must be distinct");
+    sites += states[i]->n + 1;
     if (!plans[i]) return fail(MPS_ERR_ARG, "NULL plan");
     if (plans[i]->plan.n_qubits != states[i]->n)
       return fail(MPS_ERR_ARG, "state " + std::to_string(i) + ": plan and MPS qubit counts differ");
   }
+  // one launch row per site (and two per bond for the roots)
+  if (2 * sites > 65535) return fail(MPS_ERR_ARG, "at most 32767 sites (qubits + 1 per state) per call");
   return expect_multi_impl(states, plans, count, (int)prec, energies, per_term);
 }
 

@@ -28,6 +28,7 @@ def _fragment(binding, n_s, D, layers, seed, n_strings=None, canonical=False):
     assert m.apply_gates(q0, q1, u) == len(q0)
     if canonical:
         m.canonicalize()
+    m.cap_d = D  # for copies
     h, g = random_integrals(n_s, workload_rng(500 + seed, 0))
     ps = jw_hamiltonian(h, g)
     if n_strings is not None:
@@ -53,21 +54,46 @@ def fragments(gpu_lib):
         plan.close()
 
 
+def _copies(binding, fragments):
+    out = []
+    for m, _, _ in fragments:
+        c = binding.Mps(m.n, m.cap_d, 1e-12)
+        c.copy_from(m)
+        out.append(c)
+    return out
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64", "split_f16", "split_bf16"])
 def test_multi_equals_one_by_one(fragments, prec):
     from paper_2303_03681_amd import binding
-    states = [f[0] for f in fragments]
     plans = [f[1] for f in fragments]
-    single = [m.expect(p, prec, per_term=True) for m, p in zip(states, plans)]
-    e, per = binding.expect_multi(states, plans, prec, per_term=True)
+    # fresh copies on both sides, so that the merged pass computes the
+    # boundary-environment chains itself and the single calls theirs
+    a = _copies(binding, fragments)
+    b = _copies(binding, fragments)
+    e, per = binding.expect_multi(a, plans, prec, per_term=True)
+    single = [m.expect(p, prec, per_term=True) for m, p in zip(b, plans)]
     for i, ((e1, p1), e2, p2) in enumerate(zip(single, e, per)):
         _say(f"  {prec} fragment {i}: E {e1:.15f} vs {e2:.15f}, max |d<P>| {np.max(np.abs(p1 - p2)):.1e}")
         assert e1 == e2
         assert np.array_equal(p1, p2)
-    # a subset in another order, and the merged launches again on the same plans
+    # again with the chains current, and a subset in another order
+    e2 = binding.expect_multi(a, plans, prec)
+    assert np.array_equal(e2, e)
     sub = [4, 0, 2]
-    e3 = binding.expect_multi([states[i] for i in sub], [plans[i] for i in sub], prec)
+    e3 = binding.expect_multi([a[i] for i in sub], [plans[i] for i in sub], prec)
     assert all(e3[j] == single[i][0] for j, i in enumerate(sub))
+    # after one more gate on every state: stale chains of different lengths
+    for m in a + b:
+        u = np.zeros((1, 16, 2))
+        u[0, [0, 5, 10, 15], 0] = np.cos(0.3)
+        u[0, [3, 6, 9, 12], 1] = np.sin(0.3) * np.array([1, -1, -1, 1])
+        assert m.apply_gates(np.array([0], np.int32), np.array([1], np.int32), u) == 1
+    e4 = binding.expect_multi(a, plans, prec)
+    e5 = [m.expect(p, prec) for m, p in zip(b, plans)]
+    assert all(x == y for x, y in zip(e4, e5))
+    for m in a + b:
+        m.close()
 
 
 def test_multi_small_state_vs_oracle(fragments):
