@@ -80,8 +80,9 @@ class QubitAdapt:
                     raise
                 for h, l in zip(handles, lists):
                     h.apply_gates(*l)
+            es = binding.expect_multi(handles, [self.plan] * len(handles), self.prec)
             for i, a in enumerate(idx):
-                g[a] = handles[2 * i].expect(self.plan, self.prec) - handles[2 * i + 1].expect(self.plan, self.prec)
+                g[a] = es[2 * i] - es[2 * i + 1]
         return g
 
     def iterate(self, opt_steps: int = 5, lr: float = 0.1) -> dict:

@@ -14,7 +14,8 @@ handle keeps the state after that prefix and advances by one factor at a
 time; each shifted evaluation copies it (mps_copy), applies the shifted
 factor and the unchanged suffix, and measures the energy.  Up to `batch`
 factors are evaluated together, their 2*batch gate lists in shared launches
-(mps_apply_gates_multi) when the bonds allow it.  Exact for a circuit whose
+(mps_apply_gates_multi) when the bonds allow it and their energies in one
+pass (mps_expect_pauli_sum_multi).  Exact for a circuit whose
 gates do not truncate; with truncation it is the shift rule applied to the
 truncated circuit.
 """
@@ -128,11 +129,11 @@ class ExponentialGradient:
                 for h, l in zip(handles, lists):
                     h.apply_gates(*l)
             self.gates_applied += sum(len(l[0]) for l in lists)
+            # the 2 * batch energies in one pass (launches shared by the handles)
+            es = binding.expect_multi(handles, [self.plan] * len(handles), self.prec)
             for i, k in enumerate(ks):
-                ep = handles[2 * i].expect(self.plan, self.prec)
-                em = handles[2 * i + 1].expect(self.plan, self.prec)
                 j, _, c = self.exps[k]
-                grad[j] += c * (ep - em)
+                grad[j] += c * (es[2 * i] - es[2 * i + 1])
             self.evaluations += 2 * len(ks)
         # the prefix handle now holds the whole circuit
         e = self.prefix.expect(self.plan, self.prec)

@@ -114,7 +114,11 @@ def _fake_binding():
         for h, l in zip(handles, lists):
             h.apply_gates(*l)
         return np.array([len(l[0]) for l in lists])
-    return types.SimpleNamespace(Mps=_DenseMps, MpsError=MpsError, apply_gates_multi=apply_gates_multi)
+
+    def expect_multi(handles, plans, prec):
+        return np.array([h.expect(p, prec) for h, p in zip(handles, plans)])
+    return types.SimpleNamespace(Mps=_DenseMps, MpsError=MpsError, apply_gates_multi=apply_gates_multi,
+                                 expect_multi=expect_multi)
 
 
 @pytest.mark.parametrize("batch", [1, 3])
