@@ -96,6 +96,26 @@ def test_multi_equals_one_by_one(fragments, prec):
         m.close()
 
 
+def test_multi_states_on_their_own_streams(fragments):
+    """States bound to different streams: the pass runs on the first state's
+    stream after the others' earlier work; values as one call per state."""
+    import torch
+    from paper_2303_03681_amd import binding
+    plans = [f[1] for f in fragments]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    a, b = [], []
+    for i, (m, _, _) in enumerate(fragments):
+        for side in (a, b):
+            c = binding.Mps(m.n, m.cap_d, 1e-12, stream=streams[i % 2].cuda_stream)
+            c.copy_from(m)
+            side.append(c)
+    e = binding.expect_multi(a, plans, "c128")
+    single = [m.expect(p, "c128") for m, p in zip(b, plans)]
+    assert all(x == y for x, y in zip(e, single))
+    for m in a + b:
+        m.close()
+
+
 def test_multi_small_state_vs_oracle(fragments):
     from oracle import dense_energy
     from paper_2303_03681_amd import binding
