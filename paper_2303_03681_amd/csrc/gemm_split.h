@@ -118,8 +118,20 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
   typename P::ColB hb{};
   if (m0 + a_i < M) ha = P::rowA(ctx, m0 + a_i);
   if (n0 + b_j < N) hb = P::colB(ctx, n0 + b_j);
+  // Tiles wholly inside M x N (every tile of the saturated bonds) skip the
+  // per-element bounds checks for full K-chunks; the choice is uniform per
+  // workgroup and chunk.
+  const bool inside = m0 + BM <= M && n0 + BN <= N;
   auto load_tiles = [&](int k0) {
     const int gi = m0 + a_i, gj = n0 + b_j;
+    if (inside && k0 + BK <= K) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        ra[j] = P::loadA(ctx, ha, gi, k0 + a_k + j);
+        rb[j] = P::loadB(ctx, hb, k0 + b_k + j, gj);
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int ga = k0 + a_k + j, gb = k0 + b_k + j;
