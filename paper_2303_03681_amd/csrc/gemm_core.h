@@ -130,7 +130,25 @@ __global__ __launch_bounds__(256) void cgemm_kernel(P p, int tiles_m, int tiles_
     const int gj = n0 + jj;
     if (gj < N) hb[e] = P::colB(ctx, gj);
   }
+  // Tiles wholly inside M x N skip the per-element bounds checks for full
+  // K-chunks (uniform per workgroup and chunk).
+  const bool inside = m0 + BM <= M && n0 + BN <= N;
   auto load_tiles = [&](int k0) {
+    if (inside && k0 + BK <= K) {
+#pragma unroll
+      for (int e = 0; e < A_EL; ++e) {
+        int ii, kk;
+        a_coord(e, ii, kk);
+        ra[e] = P::loadA(ctx, ha[e], m0 + ii, k0 + kk);
+      }
+#pragma unroll
+      for (int e = 0; e < B_EL; ++e) {
+        int kk, jj;
+        b_coord(e, kk, jj);
+        rb[e] = P::loadB(ctx, hb[e], k0 + kk, n0 + jj);
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < A_EL; ++e) {
       int ii, kk;
