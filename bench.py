@@ -38,7 +38,7 @@ PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}  # MI355X dense FP64 / FP32 matrix pe
 # HBM bytes per environment launch on this workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by a 256 MiB copy), environment kernels
 # unchanged since; profiles/env_gemm_traffic_50q_D256.md has the commands and figures.
-ENV_TRAFFIC_BYTES = {"c64": 442.1e6, "c128": 1026.9e6, "split_bf16": 435.4e6, "split_f16": 435.3e6}
+ENV_TRAFFIC_BYTES = {"c64": 449.7e6, "c128": 916.6e6, "split_bf16": 425.4e6, "split_f16": 425.9e6}
 METRIC = "Pauli-string expectations/s at 50q D=256 vs complex128 path; p50/p99 latency"
 
 
