@@ -34,7 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}  # MI355X dense FP64 / FP32 matrix peaks
+# MI355X dense matrix peaks: FP64, FP32, and bf16 / f16 (the split precisions' matrix cores)
+PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3, "split_bf16": 2500.0, "split_f16": 2500.0}
+SPLIT_PRODUCTS = 3  # 16-bit MFMA products per real FP32 multiply in the split precisions
 # HBM bytes per environment launch on this workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by a 256 MiB copy), environment kernels
 # unchanged since; profiles/env_gemm_traffic_50q_D256.md has the commands and figures.
@@ -304,16 +306,21 @@ def autotune_summary(binding, enabled):
 
 
 def env_roofline(tm, prec):
-    """The environment-update kernels (a10) against their MFMA peak: algorithmic
-    FLOPs of the launches over their HIP-event durations."""
+    """The environment-update kernels (a10) against the matrix-core peak of
+    their own dtype: algorithmic FLOPs of the launches over their HIP-event
+    durations.  The split precisions run each real multiply as three 16-bit
+    products, so their matrix-core work is three times the algorithmic FLOPs
+    (`achieved` counts that work; `algorithmic_tflops` the method's own)."""
     rate = tm["env_flops"] / (tm["env_ms"] * 1e-3) / 1e12 if tm["env_ms"] > 0 else 0.0
-    peak = PEAK_TFLOPS["c128" if prec == "c128" else "c64"]
+    peak = PEAK_TFLOPS[prec]
+    work = rate * (SPLIT_PRODUCTS if prec.startswith("split") else 1)
     return {
         "bound": "mfma",
-        "achieved": rate,
+        "achieved": work,
         "peak": peak,
         "unit": "TFLOP/s",
-        "frac": rate / peak,
+        "frac": work / peak,
+        "algorithmic_tflops": rate,
         "traffic": ENV_TRAFFIC_BYTES.get(prec),
         "traffic_unit": "bytes per launch (HBM, scaled PMC FETCH_SIZE + WRITE_SIZE)",
         "kernel": "cgemm_kernel<EnvG1P/EnvG2P> (transfer-matrix update)" if prec in ("c128", "c64")
