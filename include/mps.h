@@ -266,11 +266,12 @@ mps_status mps_expect_pauli_sums(mps_handle h, int32_t n_plans, const mps_pauli_
  * stream, so count states take the launches of the deepest one instead of
  * the sum; so do the set-up steps (site tensors in environment precision,
  * each depth of the boundary-environment chains, the roots).  The closing
- * traces, string values and compensated energies follow per state.  energies[i] receives state i's E; per_term (may be NULL, as may
- * any per_term[i]) receives Re<P_k> of plan i.  The values equal those of
- * count separate calls bit for bit (every tile shape accumulates in the same
- * order).  The other states' streams are synchronised after their set-up;
- * the call returns after the work is done.  Tile autotuning, graph replay and
+ * traces, string values and compensated energies follow per state.
+ * energies[i] receives state i's E; per_term (may be NULL, as may any
+ * per_term[i]) receives Re<P_k> of plan i.  The values equal those of count
+ * separate calls bit for bit (every tile shape accumulates in the same
+ * order).  Each other state's stream is synchronised before the shared
+ * launches (its earlier work done); the call returns after the work is done.  Tile autotuning, graph replay and
  * per-state timing do not apply.  MPS_ERR_ARG for count < 0, NULL arrays or
  * plans, repeated states, a qubit-count mismatch or more than 32767 sites
  * (qubits + 1 per state) in one call; count = 0 is a no-op. */
