@@ -28,7 +28,8 @@ def oracle_gate(b0, b1, lam_l, u, D, cutoff):
 def check_gate(m, g, q0, q1, u, D, cutoff):
     """Apply two-qubit gate g (packed arrays q0, q1, u) alone to the GPU state
     m and redo it in the oracle on the exported sites.  Asserts equal bond
-    dimensions; returns (max |d lambda|, |d w|, kept rank, oracle spectrum)."""
+    dimensions; returns (max |d lambda|, |d w|, kept rank, oracle spectrum,
+    the oracle's discarded weight of the gate)."""
     q = int(q0[g])
     assert int(q1[g]) == q + 1
     b0, lam_l = m.export_site(q)
@@ -40,4 +41,4 @@ def check_gate(m, g, q0, q1, u, D, cutoff):
     umat = (u[g, :, 0] + 1j * u[g, :, 1]).reshape(4, 4)
     lam_ref, dw_ref, s = oracle_gate(b0, b1, lam_l, umat, D, cutoff)
     assert lam_new.size == lam_ref.size, (g, q, lam_new.size, lam_ref.size)
-    return float(np.max(np.abs(lam_new - lam_ref))), abs(dw - dw_ref), lam_ref.size, s
+    return float(np.max(np.abs(lam_new - lam_ref))), abs(dw - dw_ref), lam_ref.size, s, dw_ref

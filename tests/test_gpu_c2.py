@@ -28,6 +28,7 @@ import os
 import numpy as np
 import pytest
 
+from tests.gate_check import check_gate
 from workloads import build_config, fuse_gates, pack_gates, workload_rng
 from workloads.circuits import uccsd_gates, uccsd_n_params
 
@@ -72,26 +73,6 @@ def test_c2_windowed_vs_oracle_d256(gpu_lib, c2):
     assert abs(e64 - e128) < 1e-6
 
 
-def _oracle_gate(b0, b1, lam_l, u, D, cutoff):
-    """The oracle's two-qubit update of sites (b0, b1) with left lambda lam_l:
-    kept normalised singular values, the gate's discarded weight, the full
-    spectrum."""
-    from oracle import MpsOracle
-    spec = {}
-
-    class Spy(MpsOracle):
-        def _svd(self, mat):
-            out = super()._svd(mat)
-            spec["s"] = out[1]
-            return out
-
-    o = Spy(2, D, cutoff)
-    o.B = [b0, b1]
-    o.lam = [np.asarray(lam_l, float), np.ones(b0.shape[2]), np.ones(1)]
-    o.apply_2q(0, u)
-    return o.lam[1], o.discarded, spec["s"]
-
-
 @pytest.mark.parametrize("D", [64, 128])
 def test_c2_every_cut_is_the_oracle_truncation(gpu_lib, c2, D):
     from paper_2303_03681_amd import binding
@@ -107,21 +88,11 @@ def test_c2_every_cut_is_the_oracle_truncation(gpu_lib, c2, D):
     for g in sorted(checked):
         if g > start:
             assert m.apply_gates(q0[start:g], q1[start:g], u[start:g]) == g - start
-        q = int(q0[g])
-        b0, lam_l = m.export_site(q)
-        b1, _ = m.export_site(q + 1)
-        d0 = m.discarded_weight()
-        assert m.apply_gates(q0[g:g + 1], q1[g:g + 1], u[g:g + 1]) == 1
-        _, lam_new = m.export_site(q + 1)
-        dw = m.discarded_weight() - d0
-        umat = (u[g, :, 0] + 1j * u[g, :, 1]).reshape(4, 4)
-        lam_ref, dw_ref, s = _oracle_gate(b0, b1, lam_l, umat, D, cutoff)
-        assert lam_new.size == lam_ref.size, (g, q, lam_new.size, lam_ref.size)
-        worst_s = max(worst_s, float(np.max(np.abs(lam_new - lam_ref))))
-        worst_w = max(worst_w, abs(dw - dw_ref))
-        assert worst_s <= 1e-12 and worst_w <= 1e-12, (g, q, worst_s, worst_w)
+        dl, ddw, k, s, dw_ref = check_gate(m, g, q0, q1, u, D, cutoff)
+        worst_s = max(worst_s, dl)
+        worst_w = max(worst_w, ddw)
+        assert worst_s <= 1e-12 and worst_w <= 1e-12, (g, worst_s, worst_w)
         disc_sum += dw_ref
-        k = lam_ref.size
         if k == D and s.size > D and s[D] > cutoff * np.linalg.norm(s):
             n_cap += 1
             min_gap = min(min_gap, (s[D - 1] - s[D]) / s[0])

@@ -98,7 +98,7 @@ def test_c2_full_uccsd_d64(gpu_lib):
             done = e
         if done < g or g == len(q0):
             break
-        dl, ddw, k, s = check_gate(m, g, q0, q1, u, D, CUTOFF)
+        dl, ddw, k, s, _ = check_gate(m, g, q0, q1, u, D, CUTOFF)
         done = g + 1
         meta["max_dlam"] = max(meta["max_dlam"], dl)
         meta["max_dw"] = max(meta["max_dw"], ddw)

@@ -100,7 +100,7 @@ def test_c5_shape_default(gpu_lib):
             assert m.apply_gates(q0[start:g], q1[start:g], u[start:g]) == g - start
         if g == len(q0):
             break
-        dl, dw, k, _ = check_gate(m, int(g), q0, q1, u, 512, w.spec.cutoff)
+        dl, dw, k, _, _ = check_gate(m, int(g), q0, q1, u, 512, w.spec.cutoff)
         checks.append((int(g), k, dl, dw))
         start = int(g) + 1
     wide = m.timing()["jacobi_wide_items"]  # counted since set_timing
