@@ -14,11 +14,19 @@
 //        of contractions); values below 2^-14 lose relative precision but keep
 //        an absolute error near 2^-24.
 //
-// The problem functors are those of cgemm_kernel (gemm_core.h) with T = float;
-// the tile loop, XCD remap and operand handles follow cgemm_kernel, with the
-// split done when a staged FP32 tile is written to LDS (8 consecutive k per
-// thread, each 16-bit plane stored as one 16-byte vector), into the second of
-// two LDS buffers while the matrix cores take the first.
+// The problem functors are those of cgemm_kernel (gemm_core.h) with T = float,
+// plus loadA8 / loadB8, which fetch the eight consecutive k of one thread's
+// row (column) in a full K-chunk and return the operation (SPLIT_* bits) that
+// maps the split planes of the fetched values to those of the operand: a
+// conjugation or a Pauli phase that is uniform over the eight values costs a
+// sign flip or a swap of whole planes instead of work on every element.
+// Negation and the exchange of real and imaginary parts commute exactly with
+// the split, so the planes equal those of the per-element fetch (up to the
+// sign of zero residuals, which no product sum sees).  The tile
+// loop, XCD remap and operand handles follow cgemm_kernel, with the split done
+// when a staged FP32 tile is written to LDS (8 consecutive k per thread, each
+// 16-bit plane stored as one 16-byte vector), into the second of two LDS
+// buffers while the matrix cores take the first.
 //
 // MFMA 16x16x32 operand layout (wave64), lane l, j = 0..7:
 //   A fragment A[l % 16][8 (l / 16) + j], B fragment B[8 (l / 16) + j][l % 16],
@@ -34,6 +42,13 @@ namespace mps {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+
+typedef float f32x8_t __attribute__((ext_vector_type(8)));
+
+// Plane operations returned by loadA8 / loadB8, applied in this order.
+constexpr int SPLIT_SWAP = 1;    // exchange the real and imaginary planes
+constexpr int SPLIT_NEG_RE = 2;  // negate the real planes
+constexpr int SPLIT_NEG_IM = 4;  // negate the imaginary planes
 
 template <typename L> struct split_traits;
 template <> struct split_traits<__bf16> {
@@ -114,6 +129,7 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
   const int b_j = P::B_CONTIG_N ? tid % BN : tid / KC;
   const int b_k = 8 * (P::B_CONTIG_N ? tid / BN : tid % KC);
   C2 ra[8], rb[8];
+  int opa = 0, opb = 0;  // plane operations of the staged values
   typename P::RowA ha{};
   typename P::ColB hb{};
   if (m0 + a_i < M) ha = P::rowA(ctx, m0 + a_i);
@@ -125,13 +141,11 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
   auto load_tiles = [&](int k0) {
     const int gi = m0 + a_i, gj = n0 + b_j;
     if (inside && k0 + BK <= K) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        ra[j] = P::loadA(ctx, ha, gi, k0 + a_k + j);
-        rb[j] = P::loadB(ctx, hb, k0 + b_k + j, gj);
-      }
+      opa = P::loadA8(ctx, ha, gi, k0 + a_k, ra);
+      opb = P::loadB8(ctx, hb, k0 + b_k, gj, rb);
       return;
     }
+    opa = opb = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int ga = k0 + a_k + j, gb = k0 + b_k + j;
@@ -139,24 +153,49 @@ __global__ __launch_bounds__(256) void cgemm_split_kernel(P p, int tiles_m, int 
       rb[j] = (gb < K && gj < N) ? P::loadB(ctx, hb, gb, gj) : make_float2(0.f, 0.f);
     }
   };
+  // The eight values of each plane as one vector: paired conversions give
+  // the leading parts, which are converted back exactly for the residuals.
   auto split8 = [](const C2 (&v)[8], V8& rh, V8& ih, V8& rl, V8& il) {
+    f32x8_t xr, xi;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const L hr0 = (L)v[j].x, hi0 = (L)v[j].y;
-      rh[j] = hr0;
-      ih[j] = hi0;
-      rl[j] = (L)((v[j].x - (float)hr0) * Tr::S);
-      il[j] = (L)((v[j].y - (float)hi0) * Tr::S);
+      xr[j] = v[j].x;
+      xi[j] = v[j].y;
+    }
+    rh = __builtin_convertvector(xr, V8);
+    ih = __builtin_convertvector(xi, V8);
+    rl = __builtin_convertvector((xr - __builtin_convertvector(rh, f32x8_t)) * Tr::S, V8);
+    il = __builtin_convertvector((xi - __builtin_convertvector(ih, f32x8_t)) * Tr::S, V8);
+  };
+  // op is uniform over the eight values of a thread (and, for the
+  // environment problems, over a wave): negations and swaps of whole planes.
+  auto plane_op = [](int op, V8& p0, V8& p1, V8& p2, V8& p3) {
+    if (op & SPLIT_SWAP) {
+      const V8 t0 = p0, t2 = p2;
+      p0 = p1;
+      p1 = t0;
+      p2 = p3;
+      p3 = t2;
+    }
+    if (op & SPLIT_NEG_RE) {
+      p0 = neg8(p0);
+      p2 = neg8(p2);
+    }
+    if (op & SPLIT_NEG_IM) {
+      p1 = neg8(p1);
+      p3 = neg8(p3);
     }
   };
   auto store_tiles = [&](int buf) {
     V8 p0, p1, p2, p3;
     split8(ra, p0, p1, p2, p3);
+    plane_op(opa, p0, p1, p2, p3);
     *(V8*)&As[buf][0][a_i][a_k] = p0;
     *(V8*)&As[buf][1][a_i][a_k] = p1;
     *(V8*)&As[buf][2][a_i][a_k] = p2;
     *(V8*)&As[buf][3][a_i][a_k] = p3;
     split8(rb, p0, p1, p2, p3);
+    plane_op(opb, p0, p1, p2, p3);
     *(V8*)&Bs[buf][0][b_j][b_k] = p0;
     *(V8*)&Bs[buf][1][b_j][b_k] = p1;
     *(V8*)&Bs[buf][2][b_j][b_k] = p2;

@@ -1236,6 +1236,20 @@ struct EnvG1P {
   }
   __device__ static C2 loadA(const Ctx&, RowA r, int, int k) { return r[k]; }
   __device__ static C2 loadB(const Ctx& c, ColB b, int k, int) { return b[(size_t)k * c.dr]; }
+  // Eight consecutive k (k + 7 < K) for the 16-bit split GEMM; the return
+  // value is the operation on the split planes that turns the loaded values
+  // into the operand (SPLIT_SWAP, SPLIT_NEG_RE, SPLIT_NEG_IM bits; none here).
+  __device__ __forceinline__ static int loadA8(const Ctx&, RowA r, int, int k, C2 (&o)[8]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) o[t] = r[k + t];
+    return 0;
+  }
+  __device__ __forceinline__ static int loadB8(const Ctx& c, ColB b, int k, int, C2 (&o)[8]) {
+    const C2* q = b + (size_t)k * c.dr;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) o[t] = q[(size_t)t * c.dr];
+    return 0;
+  }
   __device__ static void store(const Ctx& c, int i, int j, TT re, TT im) {
     C2 v;
     v.x = re;
@@ -1294,6 +1308,32 @@ struct EnvG2P {
       o.y = -v.y;
     }
     return o;
+  }
+  // Eight consecutive k as in EnvG1P: the conjugation, and the letter's
+  // phase when all eight share one s, become sign flips and a swap of the
+  // split planes (exact: the split commutes with negation); eight k across
+  // the s boundary are loaded one by one.
+  __device__ __forceinline__ static int loadA8(const Ctx& c, RowA r, int, int k, C2 (&o)[8]) {
+    const C2* q = r + (size_t)k * c.dr;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) o[t] = q[(size_t)t * c.dr];
+    return SPLIT_NEG_IM;
+  }
+  __device__ __forceinline__ static int loadB8(const Ctx& c, ColB b, int k, int j, C2 (&o)[8]) {
+    const int s = k >= c.dl;
+    const int a = k - s * c.dl;
+    if (a + 7 >= c.dl) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) o[t] = loadB(c, b, k + t, j);
+      return 0;
+    }
+    const int flip = (c.letter == 1 || c.letter == 2) ? 1 : 0;
+    const C2* q = b + (size_t)a * (2 * c.dr) + (s ^ flip) * c.dr;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) o[t] = q[(size_t)t * (2 * c.dr)];
+    if (c.letter == 2) return s == 0 ? (SPLIT_SWAP | SPLIT_NEG_IM) : (SPLIT_SWAP | SPLIT_NEG_RE);
+    if (c.letter == 3 && s == 1) return SPLIT_NEG_RE | SPLIT_NEG_IM;
+    return 0;
   }
   __device__ static void store(const Ctx& c, int i, int j, TT re, TT im) {
     C2 v;
