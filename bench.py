@@ -40,7 +40,7 @@ SPLIT_PRODUCTS = 3  # 16-bit MFMA products per real FP32 multiply in the split p
 # HBM bytes per environment launch on this workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by a 256 MiB copy), environment kernels
 # unchanged since; profiles/env_gemm_traffic_50q_D256.md has the commands and figures.
-ENV_TRAFFIC_BYTES = {"c64": 449.7e6, "c128": 916.6e6, "split_bf16": 425.4e6, "split_f16": 425.9e6}
+ENV_TRAFFIC_BYTES = {"c64": 449.7e6, "c128": 916.6e6, "split_bf16": 428.8e6, "split_f16": 430.4e6}
 METRIC = "Pauli-string expectations/s at 50q D=256 vs complex128 path; p50/p99 latency"
 
 
