@@ -215,7 +215,7 @@ mps_status mps_pauli_sum_export(mps_pauli_sum p, int32_t* left_parent, int32_t* 
 /* E = sum_k c_k Re<P_k> (Methods, UCC: the energy from the expectation
  * values of the qubit Hamiltonian; Eqs. expec1/expec2 for each <P_k>).
  * The state is not modified.  In exact canonical form (after create/reset,
- * mps_canonicalize or mps_import_site) the tries start from diag(lambda^2)
+ * mps_canonicalize or mps_import) the tries start from diag(lambda^2)
  * and the identity (Eqs. expec1, rc).  After gates, whose truncation leaves
  * the sites only nearly right-orthonormal, they start instead from the
  * identity environments of both boundaries, sum B^+ L B and sum B R B^+
@@ -291,16 +291,16 @@ mps_status mps_to_statevector(mps_handle h, double* psi);
  * NULL) receives 2*D_q*D_{q+1} complex values as (re, im) pairs in
  * [s][alpha][beta] order; lambda_left (may be NULL) receives the D_q
  * singular values of bond q. */
-mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
-                           double* lambda_left);
+mps_status mps_export(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
+                      double* lambda_left);
 
 /* Overwrite site q's tensor and the singular values of bond q.  dl must equal
  * D_{q} of the left neighbour's right bond (or 1 at q = 0) once all sites are
  * imported; the library checks shapes against its capacity only.  Importing
  * marks the state canonical: the caller asserts the imported tensors are in
  * right-canonical form with Schmidt values (use mps_canonicalize otherwise). */
-mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, const double* b,
-                           const double* lambda_left);
+mps_status mps_import(mps_handle h, int32_t q, int32_t dl, int32_t dr, const double* b,
+                      const double* lambda_left);
 
 /* Standalone one-sided Jacobi SVD (Algorithm 1) of the n_vec vectors of
  * length vec_len given row-major in `vectors` (host): the vectors are

@@ -95,8 +95,8 @@ _SIGS = {
     "mps_pauli_sum_stats": [_P, _P, _P, _P, _P],
     "mps_pauli_sum_export": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "mps_expect_pauli_sum": [_P, _P, C.c_int, _P, _P],
-    "mps_export_site": [_P, _I32, _P, _P, _P, _P],
-    "mps_import_site": [_P, _I32, _I32, _I32, _P, _P],
+    "mps_export": [_P, _I32, _P, _P, _P, _P],
+    "mps_import": [_P, _I32, _I32, _I32, _P, _P],
     "mps_jacobi_svd": [_I32, _I32, _P, _P, _P, _P],
     "mps_set_timing": [_P, _I32],
     "mps_set_fused_gates": [_P, _I32],
@@ -275,17 +275,17 @@ class Mps:
 
     def export_site(self, q: int):
         dl, dr = C.c_int32(), C.c_int32()
-        _check(_lib.mps_export_site(self._h, int(q), C.byref(dl), C.byref(dr), None, None))
+        _check(_lib.mps_export(self._h, int(q), C.byref(dl), C.byref(dr), None, None))
         b = np.zeros((2, dl.value, dr.value), np.complex128)
         lam = np.zeros(dl.value, np.float64)
-        _check(_lib.mps_export_site(self._h, int(q), C.byref(dl), C.byref(dr),
+        _check(_lib.mps_export(self._h, int(q), C.byref(dl), C.byref(dr),
                                     _ptr(b.view(np.float64)), _ptr(lam)))
         return b, lam
 
     def import_site(self, q: int, b, lam_left):
         b = _cplx(b)
         lam = np.ascontiguousarray(lam_left, dtype=np.float64)
-        _check(_lib.mps_import_site(self._h, int(q), b.shape[1], b.shape[2],
+        _check(_lib.mps_import(self._h, int(q), b.shape[1], b.shape[2],
                                     _ptr(b.view(np.float64)), _ptr(lam)))
 
     # -- expectations -------------------------------------------------------

@@ -2712,8 +2712,8 @@ mps_status mps_to_statevector(mps_handle h, double* psi) {
   return sync(h);
 }
 
-mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
-                           double* lambda_left) {
+mps_status mps_export(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, double* b,
+                      double* lambda_left) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;
   if (q < 0 || q >= h->n || !dl || !dr) return fail(MPS_ERR_ARG, "bad site or NULL outputs");
@@ -2726,8 +2726,8 @@ mps_status mps_export_site(mps_handle h, int32_t q, int32_t* dl, int32_t* dr, do
   return MPS_OK;
 }
 
-mps_status mps_import_site(mps_handle h, int32_t q, int32_t dl, int32_t dr, const double* b,
-                           const double* lambda_left) {
+mps_status mps_import(mps_handle h, int32_t q, int32_t dl, int32_t dr, const double* b,
+                      const double* lambda_left) {
   mps_status st = check_handle(h);
   if (st != MPS_OK) return st;
   if (q < 0 || q >= h->n || !b || !lambda_left) return fail(MPS_ERR_ARG, "bad site or NULL inputs");
