@@ -22,9 +22,9 @@ The loop (Server.run):
   3. requests whose gates are done get their energy (the Pauli-sum
      expectation from the boundary environments, divided by <psi|psi>; no
      canonicalisation sweep) between chunks, all of an iteration's finished
-     requests in one pass whose launches they share (mps_expect_pauli_sum_multi);
-     gradient-step requests (energy
-     and parameter-shift dE/dtheta of the fragment's UCCSD at the update's
+     requests in one pass whose launches they share
+     (mps_expect_pauli_sum_multi); gradient-step requests (energy and
+     parameter-shift dE/dtheta of the fragment's UCCSD at the update's
      angles) are also served between chunks;
   4. finished requests free their slot; arrivals are admitted between chunks.
 
