@@ -279,14 +279,14 @@ class Mps:
         b = np.zeros((2, dl.value, dr.value), np.complex128)
         lam = np.zeros(dl.value, np.float64)
         _check(_lib.mps_export(self._h, int(q), C.byref(dl), C.byref(dr),
-                                    _ptr(b.view(np.float64)), _ptr(lam)))
+                               _ptr(b.view(np.float64)), _ptr(lam)))
         return b, lam
 
     def import_site(self, q: int, b, lam_left):
         b = _cplx(b)
         lam = np.ascontiguousarray(lam_left, dtype=np.float64)
         _check(_lib.mps_import(self._h, int(q), b.shape[1], b.shape[2],
-                                    _ptr(b.view(np.float64)), _ptr(lam)))
+                               _ptr(b.view(np.float64)), _ptr(lam)))
 
     # -- expectations -------------------------------------------------------
     def expect_rows(self, psum: PauliSum, row_ptr, cols, vals, prec: str = "c128") -> np.ndarray:
